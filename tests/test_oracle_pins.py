@@ -1,0 +1,320 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: published
+generator outputs, an independent exact summation routine, Fourier closed
+forms, the continuum linear growth rate and tanh profile that follow from
+eq. (ch), the conservation law and energy decay stated with eq. (dFdt_ch),
+and a spectrally exact integrator of the spatially discrete flow (first-order
+convergence in time, as Appendix A states for the paper's ADI scheme).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from tests import refs
+
+TWO_PI = 2 * np.pi
+
+
+# --------------------------------------------------------------------------
+# Initial-condition generator
+# --------------------------------------------------------------------------
+def test_splitmix64_published_vector(orc):
+    path = os.path.join(os.path.dirname(__file__), "golden", "splitmix64_seed1234567.txt")
+    lines = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    seed = int(lines[0][1])
+    expect = [int(l[0]) for l in lines[1:]]
+    assert [orc.splitmix64(seed, k) for k in range(1, len(expect) + 1)] == expect
+    assert [refs.splitmix64_py(seed, k) for k in range(1, len(expect) + 1)] == expect
+
+
+def test_splitmix64_matches_independent_python(orc):
+    rng = np.random.default_rng(3)
+    for seed in [0, 1, 2**63 + 5, int(rng.integers(0, 2**63))]:
+        for k in [1, 2, 3, 1000, 2**40 + 7]:
+            assert orc.splitmix64(seed, k) == refs.splitmix64_py(seed, k)
+
+
+def test_init_field_definition_and_statistics(orc):
+    seed, c0, A = 99, 0.3, 0.05
+    C = orc.init_field((64, 48), c0, A, seed)
+    flat = C.ravel()
+    for s in [0, 1, 17, 64 * 48 - 1]:
+        u = (refs.splitmix64_py(seed, s + 1) >> 11) * 2.0**-53
+        assert flat[s] == c0 + A * (2.0 * u - 1.0)
+    assert abs(flat.mean() - c0) < 4 * A / math.sqrt(3 * flat.size)
+    assert abs(flat.var() - A**2 / 3) < 0.05 * A**2 / 3
+    assert flat.min() >= c0 - A and flat.max() <= c0 + A
+
+
+# --------------------------------------------------------------------------
+# Exact summation
+# --------------------------------------------------------------------------
+def test_exact_sum_matches_fsum(orc):
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(20000) * 10.0 ** rng.integers(-20, 20, 20000)
+    assert orc.exact_sum(x) == math.fsum(x)
+    y = np.array([1e100, 1.0, -1e100, 1e-100, 3.0])
+    assert orc.exact_sum(y) == math.fsum(y)
+
+
+# --------------------------------------------------------------------------
+# Stencils: Fourier eigen-relations
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("shape,k", [((32, 48), (3, 5)), ((24, 16), (0, 7)), ((8, 12, 16), (2, 1, 3))])
+def test_stencil_eigenrelations(orc, shape, k):
+    dim = len(shape)
+    L = [TWO_PI, 3.0, 5.0][:dim]
+    grids = np.meshgrid(*[np.arange(shape[a]) * (L[dim - 1 - a] / shape[a]) for a in range(dim)],
+                        indexing="ij")
+    # numpy axis a is paper axis dim-1-a; k is listed x-first
+    phase = sum(2 * np.pi * k[dim - 1 - a] / L[dim - 1 - a] * grids[a] for a in range(dim))
+    f = np.cos(phase + 0.3)
+    lam = []
+    for d in range(dim):
+        n = shape[dim - 1 - d]
+        h = L[d] / n
+        lam.append((4 / h**2) * math.sin(math.pi * k[d] / n) ** 2)
+    lap = orc.laplacian(f, L=L)
+    np.testing.assert_allclose(lap, -sum(lam) * f, atol=1e-9 * max(1.0, sum(lam)))
+    cr = orc.cross(f, L=L)
+    mixed = sum(lam[d] * lam[e] for d in range(dim) for e in range(d + 1, dim))
+    np.testing.assert_allclose(cr, mixed * f, atol=1e-9 * max(1.0, mixed))
+
+
+# --------------------------------------------------------------------------
+# Periodic pentadiagonal line solve
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,rho", [(8, 0.3), (9, 5.0), (16, 1.72), (37, 441.0), (64, 1764.0)])
+def test_line_solve_dense(orc, n, rho):
+    rng = np.random.default_rng(n)
+    f = rng.standard_normal(n)
+    A = np.eye(n)
+    for i in range(n):
+        for o, c in zip([-2, -1, 0, 1, 2], [1, -4, 6, -4, 1]):
+            A[i, (i + o) % n] += rho * c
+    y = orc.cyclic_penta_solve(rho, f)
+    np.testing.assert_allclose(y, np.linalg.solve(A, f), rtol=0, atol=1e-12 * np.abs(f).max())
+    assert np.abs(A @ y - f).max() <= 1e-13 * (1 + 16 * rho) * np.abs(f).max()
+
+
+@pytest.mark.parametrize("n,rho", [(128, 1.72), (1024, 1764.0), (256, 13.8)])
+def test_line_solve_dft_closed_form(orc, n, rho):
+    rng = np.random.default_rng(1)
+    f = rng.standard_normal(n)
+    theta = 2 * np.pi * np.arange(n) / n
+    sym = 1.0 + rho * (2 - 2 * np.cos(theta)) ** 2
+    ref = np.real(np.fft.ifft(np.fft.fft(f) / sym))
+    y = orc.cyclic_penta_solve(rho, f)
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-13 * np.abs(f).max() * max(1, rho) ** 0.5)
+
+
+# --------------------------------------------------------------------------
+# Whole linear step: single Fourier mode about a uniform state
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("k,c0,tol", [((5, 0), 0.0, 1e-12), ((5, 5), 0.0, 1e-12),
+                                     ((20, 20), 0.0, 1e-12), ((40, 7), 0.0, 1e-12),
+                                     ((5, 5), 0.3, 1e-8), ((11, 3), 0.3, 1e-8)])
+def test_single_mode_amplification(orc, k, c0, tol):
+    n, gamma, dt, eps = 128, 0.01, 1e-3, 1e-7
+    x = np.arange(n) * TWO_PI / n
+    X, Y = np.meshgrid(x, x, indexing="xy")  # Y[row]=y, X[col]=x
+    mode = np.cos(k[0] * X + k[1] * Y)
+    C1 = orc.step(c0 + eps * mode, gamma, dt, 1)
+    G = np.sum((C1 - c0) * mode) / np.sum(mode * mode) / eps
+    Gh = refs.amplification(k, (n, n), TWO_PI, gamma, dt, c0)
+    assert abs(G - Gh) <= tol * max(1.0, abs(Gh))
+
+
+def test_single_mode_amplification_3d(orc):
+    n, gamma, dt, eps, k = 16, 0.01, 5e-4, 1e-7, (2, 3, 1)
+    x = np.arange(n) * TWO_PI / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    mode = np.cos(k[0] * X + k[1] * Y + k[2] * Z)
+    C1 = orc.step(eps * mode, gamma, dt, 1)
+    G = np.sum(C1 * mode) / np.sum(mode * mode) / eps
+    assert abs(G - refs.amplification(k, (n, n, n), TWO_PI, gamma, dt, 0.0)) < 1e-12
+
+
+def test_linear_growth_rate_converges_to_continuum(orc):
+    """(G - 1)/dt of the scheme tends to sigma(k) = -k^2 (3 c0^2 - 1) - gamma k^4,
+    the growth rate of eq. (ch) linearised about c0, as h and dt shrink."""
+    gamma, eps = 0.01, 1e-7
+    for kvec, c0 in [((5, 0), 0.0), ((5, 5), 0.0), ((3, 4), 0.2)]:
+        k2 = kvec[0] ** 2 + kvec[1] ** 2
+        sigma = -k2 * (3 * c0**2 - 1) - gamma * k2**2
+        errs = []
+        for n, dt in [(32, 4e-4), (64, 1e-4), (128, 2.5e-5)]:
+            x = np.arange(n) * TWO_PI / n
+            X, Y = np.meshgrid(x, x, indexing="xy")
+            mode = np.cos(kvec[0] * X + kvec[1] * Y)
+            C1 = orc.step(c0 + eps * mode, gamma, dt, 1)
+            G = np.sum((C1 - c0) * mode) / np.sum(mode * mode) / eps
+            errs.append(abs((G - 1) / dt - sigma))
+        assert errs[0] > errs[1] > errs[2]
+        assert errs[1] / errs[2] > 3.0  # second order in h with dt ~ h^2
+        assert errs[2] < 0.02 * abs(sigma)
+
+
+# --------------------------------------------------------------------------
+# Stationary profile tanh(x / sqrt(2 gamma))
+# --------------------------------------------------------------------------
+@pytest.mark.slow
+def test_tanh_steady_state_second_order(orc):
+    gamma = 0.01
+    w = math.sqrt(2 * gamma)
+    errs = []
+    for n in (64, 128, 256):
+        x = np.arange(n) * TWO_PI / n
+        prof = np.tanh((x - TWO_PI / 4) / w) * np.tanh((3 * TWO_PI / 4 - x) / w)
+        C = np.tile(prof, (8, 1))
+        dt = 1e-3
+        for _ in range(150):
+            Cn = orc.step(C, gamma, dt, 100)
+            delta = np.abs(Cn - C).max()
+            C = Cn
+            if delta < 1e-11:  # change per 100 steps
+                break
+        assert delta < 1e-11, "did not reach the discrete steady state"
+        assert np.abs(C - C[0:1, :]).max() < 1e-12  # y-invariant field stays y-invariant
+        errs.append(np.abs(C[0] - prof).max())
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5
+    assert errs[2] < 3e-3
+
+
+# --------------------------------------------------------------------------
+# Conservation, energy decay, the dF/dt identity
+# --------------------------------------------------------------------------
+def test_conservation_and_monotone_energy_c1(orc):
+    C0 = orc.init_field((128, 128), 0.0, 0.1, 1)
+    C, S = orc.run_series(C0, 0.01, 1e-3, 2000, K=1)
+    drift = np.abs(S[:, 5] - S[0, 5]).max()
+    assert drift <= 5e-14  # rounding level over 2000 steps
+    F = S[:, 1]
+    assert np.all(np.diff(F) <= 1e-13 * F[:-1])
+    assert np.all(np.isfinite(S))
+
+
+def test_conservation_asymmetric_3d(orc):
+    C0 = orc.init_field((12, 16, 20), 0.2, 0.05, 5)
+    C, S = orc.run_series(C0, 0.01, 5e-4, 60, K=10)
+    assert np.abs(S[:, 5] - S[0, 5]).max() <= 1e-14
+    assert np.all(np.diff(S[:, 1]) <= 0)
+
+
+def test_dFdt_identity_is_derivative_of_F(orc):
+    """G_id = -prod(h) sum |grad+ mu|^2 is the derivative of the discrete F along
+    the spatially discrete flow v = lap_h mu (summation by parts)."""
+    rng = np.random.default_rng(4)
+    gamma = 0.02
+    for shape, L in [((32, 24), [TWO_PI, 4.0]), ((8, 10, 12), [3.0, 4.0, 5.0])]:
+        C = 0.2 + 0.3 * rng.standard_normal(shape)
+        mu = C**3 - C - gamma * orc.laplacian(C, L=L)
+        v = orc.laplacian(mu, L=L)
+        e = 1e-6
+        num = (orc.energy(C + e * v, gamma, L=L) - orc.energy(C - e * v, gamma, L=L)) / (2 * e)
+        G = orc.dFdt_identity(C, gamma, L=L)
+        assert G < 0
+        assert abs(num - G) <= 1e-6 * abs(G)
+
+
+def test_energy_conventions(orc):
+    C = orc.init_field((16, 16), 0.1, 0.5, 2)
+    h2 = (TWO_PI / 16) ** 2
+    Fq = orc.energy(C, 0.01, conv=0)
+    Fh = orc.energy(C, 0.01, conv=1)
+    assert abs((Fh - Fq) - 0.25 * h2 * math.fsum(((C**2 - 1) ** 2).ravel())) < 1e-12 * Fq
+
+
+def test_constant_field(orc):
+    c, gamma = 0.37, 0.01
+    C0 = np.full((16, 24), c)
+    C, S = orc.run_series(C0, gamma, 1e-3, 20, K=5)
+    assert np.abs(C - c).max() < 1e-13
+    Fexact = 0.25 * (c * c - 1) ** 2 * TWO_PI**2
+    assert np.allclose(S[:, 1], Fexact, rtol=1e-14)
+    assert np.abs(S[:, 3]).max() < 1e-25
+    assert np.abs(S[:, 2]).max() < 1e-12
+    assert np.abs(S[:, 5] - S[0, 5]).max() < 1e-14
+
+
+# --------------------------------------------------------------------------
+# Symmetries
+# --------------------------------------------------------------------------
+def test_odd_symmetry_bitwise(orc):
+    C0 = orc.init_field((32, 40), 0.1, 0.2, 8)
+    a = orc.step(C0, 0.01, 1e-3, 200)
+    b = orc.step(-C0, 0.01, 1e-3, 200)
+    assert np.array_equal(a, -b)
+
+
+def test_shift_and_transpose(orc):
+    C0 = orc.init_field((32, 32), 0.0, 0.2, 9)
+    a = orc.step(C0, 0.01, 1e-3, 50)
+    b = orc.step(np.roll(C0, 5, axis=0), 0.01, 1e-3, 50)  # shift in y
+    assert np.abs(np.roll(a, 5, axis=0) - b).max() < 1e-12
+    c = orc.step(np.roll(C0, 3, axis=1), 0.01, 1e-3, 50)  # shift in x
+    assert np.abs(np.roll(a, 3, axis=1) - c).max() < 1e-12
+    t = orc.step(np.ascontiguousarray(C0.T), 0.01, 1e-3, 50)
+    assert np.abs(t.T - a).max() < 1e-12
+
+
+def test_y_invariant_stays_1d(orc):
+    prof = orc.init_field((1, 64), 0.0, 0.3, 3)[0]
+    C = orc.step(np.tile(prof, (16, 1)), 0.01, 1e-3, 100)
+    assert np.abs(C - C[0:1]).max() < 1e-12
+    # and it follows the 1D scheme: a 16 x 64 grid equals an 8 x 64 one row by row
+    C8 = orc.step(np.tile(prof, (8, 1)), 0.01, 1e-3, 100)
+    assert np.abs(C[:8] - C8).max() < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Time accuracy against the spatially discrete flow (Appendix A: first order)
+# --------------------------------------------------------------------------
+@pytest.mark.slow
+def test_first_order_in_time_vs_semidiscrete_flow(orc):
+    n, gamma, T = 64, 0.01, 0.2
+    C0 = orc.init_field((n, n), 0.0, 0.1, 7)
+    ref = refs.semi_discrete_flow(C0, gamma, T, 1e-4)
+    Fref = orc.energy(ref, gamma)
+    eC, eF = [], []
+    for dt in (1e-3, 5e-4, 2.5e-4):
+        C = orc.step(C0, gamma, dt, int(round(T / dt)))
+        eC.append(np.abs(C - ref).max())
+        eF.append(abs(orc.energy(C, gamma) - Fref))
+    for e in (eC, eF):
+        assert 1.7 < e[0] / e[1] < 2.4 and 1.7 < e[1] / e[2] < 2.4
+    assert eC[-1] < 0.02
+
+
+# --------------------------------------------------------------------------
+# Run/series bookkeeping and determinism
+# --------------------------------------------------------------------------
+def test_series_resume_bitwise(orc):
+    C0 = orc.init_field((32, 32), 0.0, 0.1, 11)
+    full = orc.step(C0, 0.01, 1e-3, 40)
+    half = orc.step(orc.step(C0, 0.01, 1e-3, 20), 0.01, 1e-3, 20)
+    assert np.array_equal(full, half)
+
+
+def test_series_definition(orc):
+    """beta = -(t/F) dF/dt with dF/dt from the central difference of F."""
+    gamma, dt, K, N = 0.01, 1e-3, 10, 100
+    C0 = orc.init_field((32, 32), 0.0, 0.1, 12)
+    _, S = orc.run_series(C0, gamma, dt, N, K=K)
+    assert S.shape == (N // K + 1, 6)
+    F = [orc.energy(orc.step(C0, gamma, dt, k), gamma) for k in range(N + 1)]
+    for j in range(S.shape[0]):
+        k = j * K
+        assert S[j, 0] == k * dt
+        assert S[j, 1] == F[k]
+        if k == 0:
+            G = (F[1] - F[0]) / dt
+        elif k == N:
+            G = (F[N] - F[N - 1]) / dt
+        else:
+            G = (F[k + 1] - F[k - 1]) / (2 * dt)
+        assert S[j, 2] == G
+        assert S[j, 4] == (0.0 if k == 0 else -(k * dt) * G / F[k])
