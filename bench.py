@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Benchmark of the Cahn-Hilliard ensemble hot path on one MI355X.
+
+A "step" is one time step of the whole path for every member of the batch:
+the RHS + x-solve pass, the y-solve pass (and z in 3D), and the F / <C> /
+dF/dt reductions on cadence steps.  The metric is lattice-site updates per
+second (GLUPS = sites x steps / seconds / 1e9) with the state resident in HBM.
+
+Prints ONE JSON line.  Default workload: a single 1024^2 FP64 grid (the
+plain single-grid mode); the same line carries the FP32 batched ensemble
+(64 x 512^2) measured the same way, the roofline figures of the dominant
+kernel and the oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's)")
+    p.add_argument("--warmup", type=int, default=100)
+    p.add_argument("--workload", default="c2")
+    p.add_argument("--compare", default="c3", help="second workload reported in the same line ('' = none)")
+    p.add_argument("--compare-steps", type=int, default=2000)
+    p.add_argument("--kernel-steps", type=int, default=50, help="directly launched steps timed per kernel")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--autotune", action="store_true", help="autotune tile shapes first (cached)")
+    p.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1911_03386_amd", "tune_cache.txt"))
+    p.add_argument("--graph-steps", type=int, default=16)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain device copy of known size (for HBM counter calibration)")
+    return p.parse_args()
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("ch_kernels.hip", "ch_internal.h"):
+        with open(os.path.join(ROOT, "paper_1911_03386_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken with the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_src_sha") != kernel_source_sha():
+        return None
+    return t.get("workloads", {}).get(workload, {}).get(kernel)
+
+
+def run_gpu(wl, steps, warmup, kernel_steps, graph_steps, autotune, tune_cache):
+    import torch
+
+    from paper_1911_03386_amd import Ensemble
+
+    total = warmup + steps + kernel_steps + 2
+    ens = Ensemble(wl.descs, prec=wl.prec, cadence=wl.cadence, max_samples=total // wl.cadence + 2)
+    ens.set_graph_steps(graph_steps)
+    if autotune:
+        ens.autotune(tune_cache)
+    ens.init_random()
+    if warmup:
+        ens.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(ens.stream)
+    ens.step(steps)
+    ev1.record(ens.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    kms = ens.time_kernels(kernel_steps)  # per-launch ms: [x pass, y pass, z pass]
+    F, meanC = ens.energy()
+    plan = ens.describe()
+    ens.close()
+    return dict(wall=wall, gpu_ms=gpu_ms, kernel_ms=[float(x) for x in kms], plan=plan,
+                F=[float(x) for x in F[:4]])
+
+
+def copy_calibration():
+    import torch
+
+    n = 256 * 1024 * 1024  # 1 GiB of float32
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+
+
+def cpu_baseline(wl, seconds):
+    """The FP64 oracle on a bounded sample: the first member of the workload,
+    stepped until about `seconds` of CPU time is spent."""
+    import numpy as np
+
+    import oracle
+
+    d = wl.descs[0]
+    shape = tuple(d.n[a] for a in range(d.dim))[::-1]
+    L = [d.L[a] for a in range(d.dim)]
+    C = oracle.init_field(shape, d.c0, d.noise, d.seed)
+    sites = int(np.prod(shape))
+    t0 = time.perf_counter()
+    C = oracle.step(C, d.gamma, d.dt, 1, L=L)
+    one = time.perf_counter() - t0
+    k = max(1, int(seconds / max(one, 1e-6)))
+    t0 = time.perf_counter()
+    C = oracle.step(C, d.gamma, d.dt, k, L=L)
+    el = time.perf_counter() - t0
+    return {
+        "value": sites * k / el / 1e9,
+        "unit": "GLUPS",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"member 0 of {wl.name} ({'x'.join(map(str, shape[::-1]))}), {k} steps, {el:.1f} s",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "ensemble members shard across GPUs without communication, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    from paper_1911_03386_amd import CH_F32_BULK, workloads
+
+    wl = workloads.get(args.workload)
+    steps = args.steps if args.steps is not None else wl.steps
+    r = run_gpu(wl, steps, args.warmup, args.kernel_steps, args.graph_steps, args.autotune,
+                args.tune_cache)
+    S = wl.sites
+    value = S * steps / (r["gpu_ms"] / 1e3) / 1e9
+    word = 4 if wl.prec == CH_F32_BULK else 8
+    # per launch each pass reads the field once and writes it once
+    kinds = ["x_pass", "y_pass", "z_pass"]
+    kms = r["kernel_ms"]
+    dom = max(range(3), key=lambda i: kms[i])
+    alg_bytes = 2 * word * S
+    achieved = alg_bytes / (kms[dom] / 1e3) / 1e9
+    traffic = measured_traffic(wl.name, kinds[dom])
+    out = {
+        "metric": "lattice-site updates/s (GLUPS) + % HBM roofline, FP32-batched vs FP64-plain",
+        "value": round(value, 3),
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["gpu_ms"] / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if wl.prec == CH_F32_BULK else "f64",
+        "data": "synthetic (seeded uniform-noise initial conditions)",
+        "config": {"workload": wl.name, "members": len(wl.descs), "sites": S,
+                   "cadence": wl.cadence, "note": wl.note},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": kinds[dom],
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "alg_bytes_per_launch": alg_bytes,
+            "ms_per_launch": {k: round(v, 5) for k, v in zip(kinds, kms)},
+            "step_frac": round(S * 4 * word * (1.5 if wl.descs[0].dim == 3 else 1.0)
+                               / (r["gpu_ms"] / steps / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+        },
+        "plan": r["plan"].strip().splitlines(),
+        "kernel_src_sha": kernel_source_sha(),
+    }
+    if args.compare:
+        wc = workloads.get(args.compare)
+        rc = run_gpu(wc, args.compare_steps, args.warmup, args.kernel_steps, args.graph_steps,
+                     args.autotune, args.tune_cache)
+        wordc = 4 if wc.prec == CH_F32_BULK else 8
+        vc = wc.sites * args.compare_steps / (rc["gpu_ms"] / 1e3) / 1e9
+        out["compare"] = {
+            "workload": wc.name,
+            "dtype": "f32" if wc.prec == CH_F32_BULK else "f64",
+            "value": round(vc, 3),
+            "unit": "GLUPS",
+            "steps": args.compare_steps,
+            "ms_per_step": rc["gpu_ms"] / args.compare_steps,
+            "ms_per_launch": {k: round(v, 5) for k, v in zip(kinds, rc["kernel_ms"])},
+            "hbm_frac_of_step": round(wc.sites * 4 * wordc * (1.5 if wc.descs[0].dim == 3 else 1.0)
+                                      / (rc["gpu_ms"] / args.compare_steps / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+            "beats_fp64_single": vc > value,
+        }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,1127 @@
+// Host runtime of libch.so: argument validation, size classes and tile plans,
+// workspace layout, line-solve coefficients, launch sequencing, HIP graphs and
+// the autotuner.  All device work is done by the kernels in ch_kernels.hip.
+#include "../../include/ch.h"
+#include "ch_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+using namespace chk;
+
+namespace {
+
+thread_local std::string g_err;
+std::mutex g_live_mu;
+std::set<const void*> g_live;  // contexts created and not yet destroyed
+
+bool is_live(const void* p)
+{
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    return g_live.count(p) != 0;
+}
+
+constexpr size_t kAlign = 256;
+constexpr size_t kLdsLimit = 160 * 1024 - 1024;  // gfx950: 160 KiB per workgroup, minus statics
+
+size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+
+struct ColPlan {
+    int cy = 0, b = 0, P = 0;
+    int64_t cols = 0, stride = 0, outer = 0, nblocks = 0;
+};
+
+struct ClassPlan {
+    int dim = 2, nx = 0, ny = 0, nz = 1;
+    std::vector<int> members;
+    // pass A
+    int cx = 0, waves = 4, P = 0, rpw = 0, R = 0, bands = 0, pitch = 0;
+    int64_t nblocksA = 0;
+    size_t ldsA = 0;
+    ColPlan col[3];  // [1] = y, [2] = z
+    // workspace
+    size_t off_mids = 0, off_partials = 0;
+    int64_t partial_cap = 0;  // blocks
+};
+
+struct Layout {
+    size_t off_mem = 0, off_C = 0, off_W = 0, off_steps = 0, off_done = 0, off_flags = 0;
+    size_t off_series = 0, off_energy = 0, off_beta = 0, total = 0;
+    int64_t total_elems = 0;
+    std::vector<int64_t> moff;  // element offset per member
+};
+
+int elem_size(int prec) { return prec == 0 ? 8 : 4; }
+
+int lds_pos(int xx, int cx, int pad) { return xx + (xx / cx) * pad; }
+
+bool planA(ClassPlan& c, int prec, int cx, int waves)
+{
+    if (!passA_has(c.dim, cx) || c.nx % cx) return false;
+    const int P = c.nx / cx;
+    if (P < 1 || P > 64) return false;
+    if (waves < 1 || waves > kPassAThreads / 64) return false;
+    const int rpw = 64 / P;
+    const int R = waves * rpw;
+    const int pad = passA_pad(prec);
+    const int pitch = lds_pos(c.nx + 2 * kHalo - 1, cx, pad) + 1;
+    const int planes = c.dim == 3 ? 4 : 1;
+    const size_t lds = (size_t)planes * (R + 3) * pitch * elem_size(prec);
+    if (lds > kLdsLimit) return false;
+    c.cx = cx;
+    c.waves = waves;
+    c.P = P;
+    c.rpw = rpw;
+    c.R = R;
+    c.bands = (c.ny + R - 1) / R;
+    c.pitch = pitch;
+    c.ldsA = lds;
+    c.nblocksA = (int64_t)c.members.size() * c.nz * c.bands;
+    return true;
+}
+
+bool planCol(ClassPlan& c, int prec, int axis, int cy, int b)
+{
+    ColPlan& p = c.col[axis];
+    const int n = axis == 1 ? c.ny : c.nz;
+    if (!col_has(prec, cy) || n % cy) return false;
+    const int P = n / cy;
+    if (b < 1 || c.nx % b || b * P > kColMaxThreads || b * P < 1) return false;
+    p.cy = cy;
+    p.b = b;
+    p.P = P;
+    if (axis == 1) {
+        p.stride = c.nx;
+        p.cols = (int64_t)c.nx * c.nz;
+        p.outer = (int64_t)c.nx * c.ny;
+    } else {
+        p.stride = (int64_t)c.nx * c.ny;
+        p.cols = (int64_t)c.nx * c.ny;
+        p.outer = c.nx;
+    }
+    p.nblocks = (int64_t)c.members.size() * (p.cols / b);
+    return true;
+}
+
+bool default_A(ClassPlan& c, int prec)
+{
+    const int prefs[] = {16, 8, 32, 4, 64};
+    for (int waves : {4, 2, 1})
+        for (int cx : prefs)
+            if (planA(c, prec, cx, waves)) return true;
+    return false;
+}
+
+int best_b(int nx, int P)
+{
+    int b = 1;
+    for (int t = 2; t <= 64; t *= 2)
+        if (nx % t == 0 && t * P <= kColMaxThreads) b = t;
+    return b;
+}
+
+bool default_col(ClassPlan& c, int prec, int axis)
+{
+    const int n = axis == 1 ? c.ny : c.nz;
+    const int prefs[] = {16, 32, 8, 64, 4};
+    int bestcy = 0, bestb = 0, bestscore = -1;
+    for (int cy : prefs) {
+        if (!col_has(prec, cy) || n % cy) continue;
+        const int P = n / cy;
+        const int b = best_b(c.nx, P);
+        if (b * P > kColMaxThreads) continue;
+        const int score = std::min(b * elem_size(prec), 256);
+        if (score > bestscore) {
+            bestscore = score;
+            bestcy = cy;
+            bestb = b;
+        }
+    }
+    return bestcy && planCol(c, prec, axis, bestcy, bestb);
+}
+
+bool axis_ok(int n)
+{
+    if (n < 8 || n > 4096 || n % 4) return false;
+    for (int c : {4, 8, 16, 32, 64})
+        if (n % c == 0 && n / c <= 64) return true;
+    return false;
+}
+
+ch_status validate(const ch_member_desc* members, int32_t m, int prec, int32_t cadence,
+                   int64_t max_samples, std::string& err)
+{
+    if (!members || m < 1) {
+        err = "members must be non-NULL and m >= 1";
+        return CH_EINVAL;
+    }
+    if (prec != CH_F64 && prec != CH_F32_BULK) {
+        err = "unknown precision";
+        return CH_EINVAL;
+    }
+    if (cadence < 1) {
+        err = "cadence must be >= 1";
+        return CH_EINVAL;
+    }
+    if (max_samples < 1) {
+        err = "max_samples must be >= 1";
+        return CH_EINVAL;
+    }
+    for (int i = 0; i < m; ++i) {
+        const ch_member_desc& d = members[i];
+        char buf[160];
+        if (d.dim != 2 && d.dim != 3) {
+            snprintf(buf, sizeof buf, "member %d: dim must be 2 or 3", i);
+            err = buf;
+            return CH_EINVAL;
+        }
+        if (d.dim == 2 && d.n[2] != 1) {
+            snprintf(buf, sizeof buf, "member %d: n[2] must be 1 in 2D", i);
+            err = buf;
+            return CH_EINVAL;
+        }
+        for (int a = 0; a < d.dim; ++a) {
+            if (d.n[a] < 1 || !(d.L[a] > 0.0) || !std::isfinite(d.L[a])) {
+                snprintf(buf, sizeof buf, "member %d: axis %d needs n >= 1 and finite L > 0", i, a);
+                err = buf;
+                return CH_EINVAL;
+            }
+        }
+        if (!(d.gamma > 0.0) || !std::isfinite(d.gamma) || !(d.dt > 0.0) || !std::isfinite(d.dt) ||
+            !std::isfinite(d.c0) || !std::isfinite(d.noise)) {
+            snprintf(buf, sizeof buf, "member %d: gamma, dt must be finite and > 0; c0, noise finite", i);
+            err = buf;
+            return CH_EINVAL;
+        }
+        for (int a = 0; a < d.dim; ++a) {
+            if (!axis_ok(d.n[a])) {
+                snprintf(buf, sizeof buf,
+                         "member %d: n[%d] = %d unsupported (need 8..4096, a multiple of 4, n = c*P "
+                         "with c in {4,8,16,32,64}, P <= 64)",
+                         i, a, d.n[a]);
+                err = buf;
+                return CH_EUNSUPPORTED;
+            }
+        }
+    }
+    return CH_OK;
+}
+
+// Root p of rho (z-1)^4 + z^2 inside the unit disk, and the derived recursion
+// coefficients, chunk transfer matrices and ring-closure matrix.
+void axis_coef(double rho, int n, int chunk, int prec, AxisCoef& out)
+{
+    typedef long double LD;
+    typedef std::complex<LD> CX;
+    const LD s = 1.0L / std::sqrt((LD)rho);
+    const CX b(2.0L, s);                      // z^2 - (2 + i s) z + 1 = 0
+    const CX disc = std::sqrt(b * b - (LD)4.0L);
+    const CX big = (std::abs(b + disc) >= std::abs(b - disc)) ? (b + disc) / (LD)2 : (b - disc) / (LD)2;
+    const CX p = (LD)1 / big;                 // roots multiply to 1
+    LD a1 = 2.0L * p.real(), a2 = -std::norm(p);
+    if (prec == 1) {
+        a1 = (LD)(float)a1;
+        a2 = (LD)(float)a2;
+    } else {
+        a1 = (LD)(double)a1;
+        a2 = (LD)(double)a2;
+    }
+    const LD q1 = 1.0L - a1 - a2;
+    out.a1 = (double)a1;
+    out.a2 = (double)a2;
+    out.ikappa = (double)(q1 * q1);
+    auto mul = [](const LD* A, const LD* B, LD* C) {
+        LD c0 = A[0] * B[0] + A[1] * B[2], c1 = A[0] * B[1] + A[1] * B[3];
+        LD c2 = A[2] * B[0] + A[3] * B[2], c3 = A[2] * B[1] + A[3] * B[3];
+        C[0] = c0;
+        C[1] = c1;
+        C[2] = c2;
+        C[3] = c3;
+    };
+    const LD A[4] = {a1, a2, 1.0L, 0.0L};
+    LD Mc[4] = {1, 0, 0, 1};
+    for (int k = 0; k < chunk; ++k) mul(A, Mc, Mc);
+    LD pw[4] = {Mc[0], Mc[1], Mc[2], Mc[3]};
+    for (int l = 0; l < kMaxScanLevels; ++l) {
+        for (int i = 0; i < 4; ++i) out.Mp[l][i] = (double)pw[i];
+        mul(pw, pw, pw);
+    }
+    for (int i = 0; i < 4; ++i) out.M[i] = (double)Mc[i];
+    LD An[4] = {1, 0, 0, 1};
+    for (int k = 0; k < n; ++k) mul(A, An, An);
+    const LD B0 = 1 - An[0], B1 = -An[1], B2 = -An[2], B3 = 1 - An[3];
+    const LD det = B0 * B3 - B1 * B2;
+    out.W[0] = (double)(B3 / det);
+    out.W[1] = (double)(-B1 / det);
+    out.W[2] = (double)(-B2 / det);
+    out.W[3] = (double)(B0 / det);
+}
+
+void build_classes(const ch_member_desc* members, int32_t m, std::vector<ClassPlan>& classes)
+{
+    std::map<std::vector<int>, int> idx;
+    for (int i = 0; i < m; ++i) {
+        const ch_member_desc& d = members[i];
+        std::vector<int> key = {d.dim, d.n[0], d.n[1], d.dim == 3 ? d.n[2] : 1};
+        auto it = idx.find(key);
+        if (it == idx.end()) {
+            ClassPlan c;
+            c.dim = d.dim;
+            c.nx = d.n[0];
+            c.ny = d.n[1];
+            c.nz = d.dim == 3 ? d.n[2] : 1;
+            idx[key] = (int)classes.size();
+            classes.push_back(c);
+            it = idx.find(key);
+        }
+        classes[it->second].members.push_back(i);
+    }
+}
+
+bool default_plans(std::vector<ClassPlan>& classes, int prec)
+{
+    for (auto& c : classes) {
+        if (!default_A(c, prec)) return false;
+        if (!default_col(c, prec, 1)) return false;
+        if (c.dim == 3 && !default_col(c, prec, 2)) return false;
+    }
+    return true;
+}
+
+void layout(const ch_member_desc* members, int32_t m, int prec, int64_t max_samples,
+            std::vector<ClassPlan>& classes, Layout& L)
+{
+    size_t o = 0;
+    L.off_mem = o;
+    o = align_up(o + sizeof(MemberDev) * m);
+    for (auto& c : classes) {
+        c.off_mids = o;
+        o = align_up(o + sizeof(int32_t) * c.members.size());
+    }
+    L.moff.assign(m, 0);
+    int64_t e = 0;
+    for (int i = 0; i < m; ++i) {
+        const ch_member_desc& d = members[i];
+        const int64_t sites = (int64_t)d.n[0] * d.n[1] * (d.dim == 3 ? d.n[2] : 1);
+        L.moff[i] = e;
+        e += (sites + 63) / 64 * 64;
+    }
+    L.total_elems = e;
+    L.off_C = o;
+    o = align_up(o + (size_t)e * elem_size(prec));
+    L.off_W = o;
+    o = align_up(o + (size_t)e * elem_size(prec));
+    for (auto& c : classes) {
+        // enough partial slots for the smallest tile (one x-line per block)
+        c.partial_cap = (int64_t)c.members.size() * c.nz * c.ny;
+        c.off_partials = o;
+        o = align_up(o + sizeof(double) * 3 * (size_t)c.partial_cap);
+    }
+    L.off_steps = o;
+    o = align_up(o + sizeof(int64_t) * classes.size());
+    L.off_done = o;
+    o = align_up(o + sizeof(uint32_t) * classes.size());
+    L.off_flags = o;
+    o = align_up(o + sizeof(int32_t) * m);
+    L.off_series = o;
+    o = align_up(o + sizeof(double) * kSeriesSlots * (size_t)m * max_samples);
+    L.off_energy = o;
+    o = align_up(o + sizeof(double) * 4 * (size_t)m);
+    L.off_beta = o;
+    o = align_up(o + sizeof(double) * 6 * (size_t)max_samples);
+    L.total = o;
+}
+
+}  // namespace
+
+struct ch_ctx {
+    std::vector<ch_member_desc> desc;
+    int prec = 0, conv = 0, K = 10;
+    int64_t max_samples = 1;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout L;
+    std::vector<ClassPlan> classes;
+    std::vector<MemberDev> mem;
+    int64_t step = 0;
+    int graph_steps = 16;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int gexec_steps = 0;
+    std::string err;
+    std::string arch;
+
+    MemberDev* d_mem() { return reinterpret_cast<MemberDev*>(ws + L.off_mem); }
+    void* d_C() { return ws + L.off_C; }
+    void* d_W() { return ws + L.off_W; }
+    int64_t* d_steps() { return reinterpret_cast<int64_t*>(ws + L.off_steps); }
+    uint32_t* d_done() { return reinterpret_cast<uint32_t*>(ws + L.off_done); }
+    int32_t* d_flags() { return reinterpret_cast<int32_t*>(ws + L.off_flags); }
+    double* d_series() { return reinterpret_cast<double*>(ws + L.off_series); }
+    double* d_energy() { return reinterpret_cast<double*>(ws + L.off_energy); }
+    double* d_beta() { return reinterpret_cast<double*>(ws + L.off_beta); }
+};
+
+namespace {
+
+ch_status fail(ch_ctx* ctx, ch_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx)
+        ctx->err = buf;
+    else
+        g_err = buf;
+    return st;
+}
+
+#define HIPCHK(ctx, expr)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(ctx, CH_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+void fill_member_table(ch_ctx* ctx)
+{
+    const int m = (int)ctx->desc.size();
+    ctx->mem.assign(m, MemberDev{});
+    for (auto& c : ctx->classes) {
+        for (int gi : c.members) {
+            const ch_member_desc& d = ctx->desc[gi];
+            MemberDev& md = ctx->mem[gi];
+            md.off = ctx->L.moff[gi];
+            md.sites = (int64_t)d.n[0] * d.n[1] * (d.dim == 3 ? d.n[2] : 1);
+            md.vol = 1.0;
+            for (int a = 0; a < 3; ++a) {
+                const bool used = a < d.dim;
+                md.h[a] = used ? d.L[a] / d.n[a] : 1.0;
+                md.ih2[a] = used ? 1.0 / (md.h[a] * md.h[a]) : 0.0;
+                if (used) md.vol *= md.h[a];
+            }
+            md.gamma = d.gamma;
+            md.dt = d.dt;
+            for (int a = 0; a < d.dim; ++a) {
+                const double h2 = md.h[a] * md.h[a];
+                const double rho = d.gamma * d.dt / (h2 * h2);
+                const int chunk = a == 0 ? c.cx : c.col[a].cy;
+                axis_coef(rho, d.n[a], chunk, ctx->prec, md.ax[a]);
+            }
+        }
+    }
+}
+
+ch_status upload_tables(ch_ctx* ctx)
+{
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_mem(), ctx->mem.data(), sizeof(MemberDev) * ctx->mem.size(),
+                               hipMemcpyHostToDevice, ctx->stream));
+    for (auto& c : ctx->classes) {
+        std::vector<int32_t> mids(c.members.begin(), c.members.end());
+        HIPCHK(ctx, hipMemcpyAsync(ctx->ws + c.off_mids, mids.data(), sizeof(int32_t) * mids.size(),
+                                   hipMemcpyHostToDevice, ctx->stream));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return CH_OK;
+}
+
+PassAArgs passA_args(ch_ctx* ctx, int ci, int mode)
+{
+    ClassPlan& c = ctx->classes[ci];
+    PassAArgs a{};
+    a.C = ctx->d_C();
+    a.W = ctx->d_W();
+    a.mem = ctx->d_mem();
+    a.mids = reinterpret_cast<const int32_t*>(ctx->ws + c.off_mids);
+    a.nmem = (int32_t)c.members.size();
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.nz = c.nz;
+    a.P = c.P;
+    a.rows_per_wave = c.rpw;
+    a.waves = c.waves;
+    a.R = c.R;
+    a.bands_y = c.bands;
+    a.nblocks = c.nblocksA;
+    a.pitch = c.pitch;
+    a.mode = mode;
+    a.conv = ctx->conv;
+    a.K = ctx->K;
+    a.max_samples = ctx->max_samples;
+    a.partials = reinterpret_cast<double*>(ctx->ws + c.off_partials);
+    a.done = ctx->d_done() + ci;
+    a.step = ctx->d_steps() + ci;
+    a.series = ctx->d_series();
+    a.energy_now = ctx->d_energy();
+    a.flags = ctx->d_flags();
+    return a;
+}
+
+ColArgs col_args(ch_ctx* ctx, int ci, int axis, const void* src, void* dst)
+{
+    ClassPlan& c = ctx->classes[ci];
+    const ColPlan& p = c.col[axis];
+    ColArgs a{};
+    a.src = src;
+    a.dst = dst;
+    a.mem = ctx->d_mem();
+    a.mids = reinterpret_cast<const int32_t*>(ctx->ws + c.off_mids);
+    a.axis = axis;
+    a.n = axis == 1 ? c.ny : c.nz;
+    a.stride = p.stride;
+    a.nx = c.nx;
+    a.outer = p.outer;
+    a.cols = p.cols;
+    a.b = p.b;
+    a.P = p.P;
+    a.nblocks = p.nblocks;
+    return a;
+}
+
+hipError_t launch_A(ch_ctx* ctx, int ci, int mode)
+{
+    ClassPlan& c = ctx->classes[ci];
+    PassAArgs a = passA_args(ctx, ci, mode);
+    return launch_passA(ctx->prec, c.dim, c.cx, a, c.ldsA, ctx->stream);
+}
+
+// the column sweeps of one step: 2D  w -> C ;  3D  w -> w (y), w -> C (z)
+hipError_t launch_cols(ch_ctx* ctx, int ci, int axis)
+{
+    ClassPlan& c = ctx->classes[ci];
+    void* W = ctx->d_W();
+    void* C = ctx->d_C();
+    void* dst = (axis == c.dim - 1) ? C : W;
+    return launch_col(ctx->prec, c.col[axis].cy, col_args(ctx, ci, axis, W, dst), ctx->stream);
+}
+
+hipError_t enqueue_step(ch_ctx* ctx)
+{
+    const int nc = (int)ctx->classes.size();
+    hipError_t e;
+    for (int ci = 0; ci < nc; ++ci)
+        if ((e = launch_A(ctx, ci, MODE_STEP)) != hipSuccess) return e;
+    for (int ci = 0; ci < nc; ++ci)
+        if ((e = launch_cols(ctx, ci, 1)) != hipSuccess) return e;
+    for (int ci = 0; ci < nc; ++ci)
+        if (ctx->classes[ci].dim == 3 && (e = launch_cols(ctx, ci, 2)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+hipError_t enqueue_diag(ch_ctx* ctx)
+{
+    hipError_t e;
+    for (int ci = 0; ci < (int)ctx->classes.size(); ++ci)
+        if ((e = launch_A(ctx, ci, MODE_DIAG)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+void drop_graph(ch_ctx* ctx)
+{
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->gexec = nullptr;
+    ctx->graph = nullptr;
+    ctx->gexec_steps = 0;
+}
+
+ch_status ensure_graph(ch_ctx* ctx, int steps)
+{
+    if (ctx->gexec && ctx->gexec_steps == steps) return CH_OK;
+    drop_graph(ctx);
+    HIPCHK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < steps && e == hipSuccess; ++i) e = enqueue_step(ctx);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(ctx, CH_EDEVICE, "graph capture failed: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(ctx, CH_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    }
+    ctx->graph = g;
+    ctx->gexec = ex;
+    ctx->gexec_steps = steps;
+    return CH_OK;
+}
+
+bool need_diag(int64_t n, int K)
+{
+    return (n % K) == 0 || (n >= 1 && ((n - 1) % K) == 0) || (((n + 1) % K) == 0);
+}
+
+ch_status check_ctx(ch_ctx* ctx)
+{
+    if (!ctx) return fail(nullptr, CH_EINVAL, "ctx is NULL");
+    if (!is_live(ctx)) return fail(nullptr, CH_ESTATE, "unknown or destroyed context");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(ctx, CH_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+    return CH_OK;
+}
+
+std::string plan_text(const ch_ctx* ctx)
+{
+    std::string s;
+    char buf[320];
+    for (const auto& c : ctx->classes) {
+        snprintf(buf, sizeof buf, "%dD %dx%dx%d %s x%zu: A cx=%d P=%d waves=%d R=%d blocks=%lld lds=%zu",
+                 c.dim, c.nx, c.ny, c.nz, ctx->prec ? "f32" : "f64", c.members.size(), c.cx, c.P,
+                 c.waves, c.R, (long long)c.nblocksA, c.ldsA);
+        s += buf;
+        for (int a = 1; a < c.dim; ++a) {
+            snprintf(buf, sizeof buf, " | %c cy=%d P=%d b=%d blocks=%lld", a == 1 ? 'y' : 'z',
+                     c.col[a].cy, c.col[a].P, c.col[a].b, (long long)c.col[a].nblocks);
+            s += buf;
+        }
+        s += "\n";
+    }
+    return s;
+}
+
+std::string class_key(const ch_ctx* ctx, const ClassPlan& c)
+{
+    char buf[128];
+    snprintf(buf, sizeof buf, "%s:%s:%dD:%dx%dx%d:m%zu", ctx->arch.c_str(), ctx->prec ? "f32" : "f64",
+             c.dim, c.nx, c.ny, c.nz, c.members.size());
+    return buf;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* ch_version(void) { return "ch-mi355x 0.1"; }
+
+const char* ch_last_error(const ch_ctx* ctx)
+{
+    if (ctx && is_live(ctx)) return ctx->err.c_str();
+    return g_err.c_str();
+}
+
+size_t ch_workspace_bytes(const ch_member_desc* members, int32_t m, ch_precision prec,
+                          int32_t cadence, int64_t max_samples)
+{
+    std::string err;
+    if (validate(members, m, prec, cadence, max_samples, err) != CH_OK) {
+        g_err = err;
+        return 0;
+    }
+    std::vector<ClassPlan> classes;
+    build_classes(members, m, classes);
+    if (!default_plans(classes, prec)) {
+        g_err = "no tile shape fits a size class in LDS";
+        return 0;
+    }
+    Layout L;
+    layout(members, m, prec, max_samples, classes, L);
+    return L.total;
+}
+
+ch_status ch_create(const ch_member_desc* members, int32_t m, ch_precision prec,
+                    ch_energy_conv conv, int32_t cadence, int64_t max_samples, void* d_workspace,
+                    size_t ws_bytes, void* hip_stream, ch_ctx** out)
+{
+    if (!out) return fail(nullptr, CH_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::string err;
+    ch_status st = validate(members, m, prec, cadence, max_samples, err);
+    if (st != CH_OK) return fail(nullptr, st, "%s", err.c_str());
+    if (conv != CH_ENERGY_QUARTER && conv != CH_ENERGY_PAPER_PRINTED)
+        return fail(nullptr, CH_EINVAL, "unknown energy convention");
+    if (!d_workspace) return fail(nullptr, CH_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign)
+        return fail(nullptr, CH_EINVAL, "workspace must be 256-byte aligned");
+
+    ch_ctx* ctx = new (std::nothrow) ch_ctx;
+    if (!ctx) return fail(nullptr, CH_ENOMEM, "host allocation failed");
+    ctx->desc.assign(members, members + m);
+    ctx->prec = prec;
+    ctx->conv = conv;
+    ctx->K = cadence;
+    ctx->max_samples = max_samples;
+    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    ctx->ws = reinterpret_cast<char*>(d_workspace);
+    ctx->ws_bytes = ws_bytes;
+    build_classes(members, m, ctx->classes);
+    if (!default_plans(ctx->classes, prec)) {
+        delete ctx;
+        return fail(nullptr, CH_EUNSUPPORTED, "no tile shape fits a size class in LDS");
+    }
+    layout(members, m, prec, max_samples, ctx->classes, ctx->L);
+    if (ws_bytes < ctx->L.total) {
+        size_t need = ctx->L.total;
+        delete ctx;
+        return fail(nullptr, CH_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    }
+    hipError_t e = hipGetDevice(&ctx->device);
+    if (e != hipSuccess) {
+        delete ctx;
+        return fail(nullptr, CH_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) {
+        ctx->arch = prop.gcnArchName;
+        size_t colon = ctx->arch.find(':');
+        if (colon != std::string::npos) ctx->arch.resize(colon);
+    }
+    fill_member_table(ctx);
+    st = upload_tables(ctx);
+    if (st != CH_OK) {
+        g_err = ctx->err;
+        delete ctx;
+        return st;
+    }
+    // zero fields, reset counters and series
+    for (int i = 0; i < m; ++i) {
+        e = launch_init_member(prec, static_cast<char*>(ctx->d_C()) + ctx->L.moff[i] * elem_size(prec),
+                               ctx->mem[i].sites, 0, 0.0, 0.0, ctx->stream);
+        if (e != hipSuccess) break;
+    }
+    if (e == hipSuccess)
+        e = launch_reset(ctx->d_steps(), (int)ctx->classes.size(), 0, ctx->d_done(),
+                         (int)ctx->classes.size(), ctx->d_flags(), m, ctx->d_series(),
+                         (int64_t)kSeriesSlots * m * max_samples, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        delete ctx;
+        return fail(nullptr, CH_EDEVICE, "initialisation failed: %s", hipGetErrorString(e));
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        g_live.insert(ctx);
+    }
+    *out = ctx;
+    return CH_OK;
+}
+
+ch_status ch_init_random(ch_ctx* ctx)
+{
+    ch_status st = check_ctx(ctx);
+    if (st != CH_OK) return st;
+    const int m = (int)ctx->desc.size();
+    for (int i = 0; i < m; ++i) {
+        const ch_member_desc& d = ctx->desc[i];
+        HIPCHK(ctx, launch_init_member(ctx->prec,
+                                       static_cast<char*>(ctx->d_C()) + ctx->L.moff[i] * elem_size(ctx->prec),
+                                       ctx->mem[i].sites, d.seed, d.c0, d.noise, ctx->stream));
+    }
+    HIPCHK(ctx, launch_reset(ctx->d_steps(), (int)ctx->classes.size(), 0, ctx->d_done(),
+                             (int)ctx->classes.size(), ctx->d_flags(), m, ctx->d_series(),
+                             (int64_t)kSeriesSlots * m * ctx->max_samples, ctx->stream));
+    ctx->step = 0;
+    return CH_OK;
+}
+
+ch_status ch_set_field(ch_ctx* ctx, int32_t member, const double* src)
+{
+    ch_status st = check_ctx(ctx);
+    if (st != CH_OK) return st;
+    if (member < 0 || member >= (int)ctx->desc.size() || !src)
+        return fail(ctx, CH_EINVAL, "bad member index or NULL source");
+    const int64_t sites = ctx->mem[member].sites;
+    char* dst = static_cast<char*>(ctx->d_C()) + ctx->L.moff[member] * elem_size(ctx->prec);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->prec == CH_F64) {
+        HIPCHK(ctx, hipMemcpyAsync(dst, src, sizeof(double) * sites, hipMemcpyHostToDevice, ctx->stream));
+    } else {
+        std::vector<float> tmp(sites);
+        for (int64_t i = 0; i < sites; ++i) tmp[i] = (float)src[i];
+        HIPCHK(ctx, hipMemcpyAsync(dst, tmp.data(), sizeof(float) * sites, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return CH_OK;
+}
+
+ch_status ch_get_field(ch_ctx* ctx, int32_t member, double* dst)
+{
+    ch_status st = check_ctx(ctx);
+    if (st != CH_OK) return st;
+    if (member < 0 || member >= (int)ctx->desc.size() || !dst)
+        return fail(ctx, CH_EINVAL, "bad member index or NULL destination");
+    const int64_t sites = ctx->mem[member].sites;
+    const char* src = static_cast<const char*>(ctx->d_C()) + ctx->L.moff[member] * elem_size(ctx->prec);
+    if (ctx->prec == CH_F64) {
+        HIPCHK(ctx, hipMemcpyAsync(dst, src, sizeof(double) * sites, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    } else {
+        std::vector<float> tmp(sites);
+        HIPCHK(ctx, hipMemcpyAsync(tmp.data(), src, sizeof(float) * sites, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        for (int64_t i = 0; i < sites; ++i) dst[i] = (double)tmp[i];
+    }
+    return CH_OK;
+}
+
+ch_status ch_get_step(const ch_ctx* ctx, int64_t* n)
+{
+    if (!ctx || !n) return fail(nullptr, CH_EINVAL, "NULL argument");
+    if (!is_live(ctx)) return fail(nullptr, CH_ESTATE, "unknown or destroyed context");
+    *n = ctx->step;
+    return CH_OK;
+}
+
+ch_status ch_set_step(ch_ctx* ctx, int64_t n)
+{
+    ch_status st = check_ctx(ctx);
+    if (st != CH_OK) return st;
+    if (n < 0) return fail(ctx, CH_EINVAL, "step must be >= 0");
+    if (n / ctx->K >= ctx->max_samples) return fail(ctx, CH_ESTATE, "step beyond the sample capacity");
+    const int m = (int)ctx->desc.size();
+    HIPCHK(ctx, launch_reset(ctx->d_steps(), (int)ctx->classes.size(), n, ctx->d_done(),
+                             (int)ctx->classes.size(), ctx->d_flags(), 0, ctx->d_series(),
+                             (int64_t)kSeriesSlots * m * ctx->max_samples, ctx->stream));
+    ctx->step = n;
+    return CH_OK;
+}
+
+ch_status ch_step(ch_ctx* ctx, int64_t nsteps)
+{
+    ch_status st = check_ctx(ctx);
+    if (st != CH_OK) return st;
+    if (nsteps < 0) return fail(ctx, CH_EINVAL, "nsteps must be >= 0");
+    const int64_t target = ctx->step + nsteps;
+    if (target / ctx->K >= ctx->max_samples)
+        return fail(ctx, CH_ESTATE, "step %lld would exceed max_samples = %lld at cadence %d",
+                    (long long)target, (long long)ctx->max_samples, ctx->K);
+    int64_t left = nsteps;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIPCHK(ctx, hipStreamIsCapturing(ctx->stream, &cap));
+    // the legacy null stream cannot be captured: launch directly there
+    const bool use_graph =
+        ctx->graph_steps > 0 && cap == hipStreamCaptureStatusNone && ctx->stream != nullptr;
+    if (use_graph && left >= ctx->graph_steps) {
+        st = ensure_graph(ctx, ctx->graph_steps);
+        if (st != CH_OK) return st;
+        while (left >= ctx->graph_steps) {
+            HIPCHK(ctx, hipGraphLaunch(ctx->gexec, ctx->stream));
+            left -= ctx->graph_steps;
+        }
+    }
+    for (; left > 0; --left) HIPCHK(ctx, enqueue_step(ctx));
+    ctx->step = target;
+    if (nsteps > 0 && need_diag(target, ctx->K)) HIPCHK(ctx, enqueue_diag(ctx));
+    return CH_OK;
+}
+
+ch_status ch_energy(ch_ctx* ctx, double* F, double* meanC)
+{
+    ch_status st = check_ctx(ctx);
+    if (st != CH_OK) return st;
+    const int m = (int)ctx->desc.size();
+    HIPCHK(ctx, enqueue_diag(ctx));
+    std::vector<double> en(4 * (size_t)m);
+    std::vector<int32_t> flags(m);
+    HIPCHK(ctx, hipMemcpyAsync(en.data(), ctx->d_energy(), sizeof(double) * en.size(),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(flags.data(), ctx->d_flags(), sizeof(int32_t) * m,
+                               hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    bool bad = false;
+    for (int i = 0; i < m; ++i) {
+        if (F) F[i] = en[4 * i + 0];
+        if (meanC) meanC[i] = en[4 * i + 1];
+        bad |= flags[i] != 0;
+    }
+    if (bad) return fail(ctx, CH_ENONFINITE, "non-finite free energy in at least one member");
+    return CH_OK;
+}
+
+ch_status ch_beta_series(ch_ctx* ctx, int32_t member, double* t, double* F, double* dFdt,
+                         double* dFdt_identity, double* beta, double* meanC, int64_t cap,
+                         int64_t* count)
+{
+    ch_status st = check_ctx(ctx);
+    if (st != CH_OK) return st;
+    if (member < 0 || member >= (int)ctx->desc.size() || cap < 0 || !count)
+        return fail(ctx, CH_EINVAL, "bad member, cap or NULL count");
+    int64_t J = std::min<int64_t>(ctx->step / ctx->K + 1, ctx->max_samples);
+    J = std::min<int64_t>(J, cap);
+    *count = J;
+    const double dt = ctx->desc[member].dt;
+    HIPCHK(ctx, launch_beta(ctx->d_series(), ctx->max_samples, member, ctx->K, ctx->step, dt,
+                            ctx->d_beta(), J, ctx->stream));
+    std::vector<double> buf(6 * (size_t)J);
+    int32_t flag = 0;
+    if (J > 0)
+        HIPCHK(ctx, hipMemcpyAsync(buf.data(), ctx->d_beta(), sizeof(double) * buf.size(),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(&flag, ctx->d_flags() + member, sizeof(int32_t), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    double* cols[6] = {t, F, dFdt, dFdt_identity, beta, meanC};
+    for (int c = 0; c < 6; ++c)
+        if (cols[c])
+            for (int64_t j = 0; j < J; ++j) cols[c][j] = buf[6 * j + c];
+    if (flag) return fail(ctx, CH_ENONFINITE, "non-finite free energy in member %d", member);
+    return CH_OK;
+}
+
+ch_status ch_set_graph_steps(ch_ctx* ctx, int32_t graph_steps)
+{
+    ch_status st = check_ctx(ctx);
+    if (st != CH_OK) return st;
+    if (graph_steps < 0) return fail(ctx, CH_EINVAL, "graph_steps must be >= 0");
+    ctx->graph_steps = graph_steps;
+    drop_graph(ctx);
+    return CH_OK;
+}
+
+ch_status ch_describe(const ch_ctx* ctx, char* buf, size_t cap)
+{
+    if (!ctx || !buf || cap == 0) return fail(nullptr, CH_EINVAL, "NULL argument");
+    if (!is_live(ctx)) return fail(nullptr, CH_ESTATE, "unknown or destroyed context");
+    std::string s = plan_text(ctx);
+    snprintf(buf, cap, "%s", s.c_str());
+    return CH_OK;
+}
+
+ch_status ch_time_kernels(ch_ctx* ctx, int64_t nsteps, double* ms)
+{
+    ch_status st = check_ctx(ctx);
+    if (st != CH_OK) return st;
+    if (nsteps < 1 || !ms) return fail(ctx, CH_EINVAL, "nsteps >= 1 and ms required");
+    if ((ctx->step + nsteps) / ctx->K >= ctx->max_samples)
+        return fail(ctx, CH_ESTATE, "sample capacity exceeded");
+    const int nc = (int)ctx->classes.size();
+    std::vector<hipEvent_t> ev(4 * (size_t)nsteps, nullptr);
+    for (auto& e : ev) HIPCHK(ctx, hipEventCreate(&e));
+    hipError_t e = hipSuccess;
+    for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
+        hipEvent_t* E = &ev[4 * s];
+        e = hipEventRecord(E[0], ctx->stream);
+        for (int ci = 0; ci < nc && e == hipSuccess; ++ci) e = launch_A(ctx, ci, MODE_STEP);
+        if (e == hipSuccess) e = hipEventRecord(E[1], ctx->stream);
+        for (int ci = 0; ci < nc && e == hipSuccess; ++ci) e = launch_cols(ctx, ci, 1);
+        if (e == hipSuccess) e = hipEventRecord(E[2], ctx->stream);
+        for (int ci = 0; ci < nc && e == hipSuccess; ++ci)
+            if (ctx->classes[ci].dim == 3) e = launch_cols(ctx, ci, 2);
+        if (e == hipSuccess) e = hipEventRecord(E[3], ctx->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    double acc[3] = {0, 0, 0};
+    for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
+        for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+            float f = 0;
+            e = hipEventElapsedTime(&f, ev[4 * s + k], ev[4 * s + k + 1]);
+            acc[k] += f;
+        }
+    }
+    for (auto& x : ev) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return fail(ctx, CH_EDEVICE, "kernel timing failed: %s", hipGetErrorString(e));
+    ctx->step += nsteps;
+    if (need_diag(ctx->step, ctx->K)) HIPCHK(ctx, enqueue_diag(ctx));
+    for (int k = 0; k < 3; ++k) ms[k] = acc[k] / nsteps;
+    return CH_OK;
+}
+
+ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
+{
+    ch_status st = check_ctx(ctx);
+    if (st != CH_OK) return st;
+    // cached choices: one line per class "key cx waves cy_y b_y cy_z b_z"
+    std::map<std::string, std::vector<int>> cache;
+    if (cache_path) {
+        if (FILE* f = fopen(cache_path, "r")) {
+            char key[256];
+            int v[6];
+            while (fscanf(f, "%255s %d %d %d %d %d %d", key, &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) == 7)
+                cache[key] = std::vector<int>(v, v + 6);
+            fclose(f);
+        }
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    auto time_it = [&](auto&& launch, float& ms) -> hipError_t {
+        hipError_t e = launch();  // warm-up
+        if (e != hipSuccess) return e;
+        const int reps = 5;
+        if ((e = hipEventRecord(e0, ctx->stream)) != hipSuccess) return e;
+        for (int r = 0; r < reps; ++r)
+            if ((e = launch()) != hipSuccess) return e;
+        if ((e = hipEventRecord(e1, ctx->stream)) != hipSuccess) return e;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+        e = hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        return e;
+    };
+    hipError_t err = hipSuccess;
+    for (int ci = 0; ci < (int)ctx->classes.size() && err == hipSuccess; ++ci) {
+        ClassPlan& c = ctx->classes[ci];
+        const std::string key = class_key(ctx, c);
+        auto hit = cache.find(key);
+        if (hit != cache.end()) {
+            const std::vector<int>& v = hit->second;
+            ClassPlan t = c;
+            bool ok = planA(t, ctx->prec, v[0], v[1]) && planCol(t, ctx->prec, 1, v[2], v[3]) &&
+                      (c.dim == 2 || planCol(t, ctx->prec, 2, v[4], v[5]));
+            if (ok) {
+                c = t;
+                continue;
+            }
+        }
+        // pass A candidates (timing mode: reads C, writes the scratch field)
+        float best = 1e30f;
+        int bcx = c.cx, bw = c.waves;
+        for (int waves : {4, 2, 1})
+            for (int cx : {4, 8, 16, 32, 64}) {
+                ClassPlan t = c;
+                if (!planA(t, ctx->prec, cx, waves)) continue;
+                ctx->classes[ci] = t;
+                fill_member_table(ctx);
+                if ((st = upload_tables(ctx)) != CH_OK) {
+                    ctx->classes[ci] = c;
+                    return st;
+                }
+                float ms = 0;
+                err = time_it([&] { return launch_A(ctx, ci, MODE_TIMING); }, ms);
+                if (err != hipSuccess) break;
+                if (ms < best) {
+                    best = ms;
+                    bcx = cx;
+                    bw = waves;
+                }
+            }
+        ctx->classes[ci] = c;
+        if (err != hipSuccess) break;
+        planA(c, ctx->prec, bcx, bw);
+        ctx->classes[ci] = c;
+        // column sweeps, in place on the scratch field
+        for (int axis = 1; axis < c.dim && err == hipSuccess; ++axis) {
+            const int n = axis == 1 ? c.ny : c.nz;
+            float bestc = 1e30f;
+            int bcy = c.col[axis].cy, bb = c.col[axis].b;
+            for (int cy : {4, 8, 16, 32, 64}) {
+                if (!col_has(ctx->prec, cy) || n % cy) continue;
+                for (int b = 1; b <= 64; b *= 2) {
+                    ClassPlan t = c;
+                    if (!planCol(t, ctx->prec, axis, cy, b)) continue;
+                    if (b * t.col[axis].P < 64 && b < 64 && c.nx % (2 * b) == 0 &&
+                        2 * b * t.col[axis].P <= kColMaxThreads)
+                        continue;  // a wider block is available
+                    ctx->classes[ci] = t;
+                    fill_member_table(ctx);
+                    if ((st = upload_tables(ctx)) != CH_OK) {
+                        ctx->classes[ci] = c;
+                        return st;
+                    }
+                    float ms = 0;
+                    void* W = ctx->d_W();
+                    err = time_it(
+                        [&] {
+                            return launch_col(ctx->prec, cy, col_args(ctx, ci, axis, W, W), ctx->stream);
+                        },
+                        ms);
+                    if (err != hipSuccess) break;
+                    if (ms < bestc) {
+                        bestc = ms;
+                        bcy = cy;
+                        bb = b;
+                    }
+                }
+                if (err != hipSuccess) break;
+            }
+            planCol(c, ctx->prec, axis, bcy, bb);
+            ctx->classes[ci] = c;
+        }
+        cache[key] = {c.cx, c.waves, c.col[1].cy, c.col[1].b, c.dim == 3 ? c.col[2].cy : 0,
+                      c.dim == 3 ? c.col[2].b : 0};
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    fill_member_table(ctx);
+    st = upload_tables(ctx);
+    drop_graph(ctx);
+    if (err != hipSuccess) return fail(ctx, CH_EDEVICE, "autotune: %s", hipGetErrorString(err));
+    if (st != CH_OK) return st;
+    if (cache_path) {
+        if (FILE* f = fopen(cache_path, "w")) {
+            for (auto& kv : cache)
+                fprintf(f, "%s %d %d %d %d %d %d\n", kv.first.c_str(), kv.second[0], kv.second[1],
+                        kv.second[2], kv.second[3], kv.second[4], kv.second[5]);
+            fclose(f);
+        }
+    }
+    return CH_OK;
+}
+
+ch_status ch_num_classes(const ch_ctx* ctx, int32_t* nclasses)
+{
+    if (!ctx || !nclasses) return fail(nullptr, CH_EINVAL, "NULL argument");
+    if (!is_live(ctx)) return fail(nullptr, CH_ESTATE, "unknown or destroyed context");
+    *nclasses = (int32_t)ctx->classes.size();
+    return CH_OK;
+}
+
+ch_status ch_set_tiles(ch_ctx* ctx, int32_t cls, int32_t cx, int32_t waves, int32_t cy, int32_t by,
+                       int32_t cz, int32_t bz)
+{
+    ch_status st = check_ctx(ctx);
+    if (st != CH_OK) return st;
+    if (cls < 0 || cls >= (int)ctx->classes.size()) return fail(ctx, CH_EINVAL, "bad class index");
+    ClassPlan t = ctx->classes[cls];
+    if (!planA(t, ctx->prec, cx, waves) || !planCol(t, ctx->prec, 1, cy, by) ||
+        (t.dim == 3 && !planCol(t, ctx->prec, 2, cz, bz)))
+        return fail(ctx, CH_EUNSUPPORTED, "tile shape not valid for class %d", cls);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->classes[cls] = t;
+    fill_member_table(ctx);
+    st = upload_tables(ctx);
+    drop_graph(ctx);
+    return st;
+}
+
+ch_status ch_destroy(ch_ctx* ctx)
+{
+    if (!ctx) return fail(nullptr, CH_EINVAL, "ctx is NULL");
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        if (!g_live.erase(ctx)) return fail(nullptr, CH_ESTATE, "unknown or destroyed context");
+    }
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    drop_graph(ctx);
+    delete ctx;
+    return CH_OK;
+}
+
+ch_status ch_solver_coefficients(double rho, int32_t n, int32_t chunk, int32_t prec, double* out)
+{
+    if (!out || !(rho > 0.0) || n < 1 || chunk < 1 || (prec != 0 && prec != 1))
+        return fail(nullptr, CH_EINVAL, "bad arguments");
+    AxisCoef c;
+    axis_coef(rho, n, chunk, prec, c);
+    out[0] = c.a1;
+    out[1] = c.a2;
+    out[2] = c.ikappa;
+    for (int i = 0; i < 4; ++i) out[3 + i] = c.M[i];
+    for (int i = 0; i < 4; ++i) out[7 + i] = c.W[i];
+    return CH_OK;
+}
+
+}  // extern "C"

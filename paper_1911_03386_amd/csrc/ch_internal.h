@@ -1,0 +1,102 @@
+// Internal types shared by the host runtime (ch_host.cpp) and the kernels
+// (ch_kernels.hip).  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace chk {
+
+constexpr int kMaxScanLevels = 7;  // (A^c)^(2^s), s < 7: enough for P <= 128 chunks
+constexpr int kSeriesSlots = 5;    // F(jK-1), F(jK), F(jK+1), <C>(jK), G_id(jK)
+constexpr int kPassAThreads = 256; // 4 wavefronts
+constexpr int kColMaxThreads = 512;
+constexpr int kHalo = 2;           // halo columns kept on each side of an LDS row
+
+// Coefficients of the periodic solve (I + rho [1,-4,6,-4,1]) y = x along one
+// axis of one member, factored as y = ikappa * Qa^{-1} Qc^{-1} x with the
+// causal recursion Qc^{-1}: u_i = x_i + a1 u_{i-1} + a2 u_{i-2} and its
+// mirror image Qa^{-1} (a1 = 2 Re p, a2 = -|p|^2, p the root of
+// rho (z-1)^4 + z^2 inside the unit circle).  A recursion state is the pair
+// (u_i, u_{i-1}); one element advances it by the companion matrix
+// A = [[a1, a2], [1, 0]].
+struct AxisCoef {
+    double a1, a2, ikappa;
+    double M[4];                     // A^c, c = chunk length (row-major)
+    double Mp[kMaxScanLevels][4];    // (A^c)^(2^s)
+    double W[4];                     // (I - A^n)^{-1}, n = line length
+};
+
+struct MemberDev {
+    int64_t off;       // element offset of this member in the field arrays
+    int64_t sites;
+    double h[3];
+    double ih2[3];     // 1 / h^2
+    double gamma, dt;
+    double vol;        // prod h
+    AxisCoef ax[3];
+};
+
+// Step kernel modes.
+enum : int { MODE_STEP = 0, MODE_DIAG = 1, MODE_TIMING = 2 };
+
+struct PassAArgs {
+    const void* C;             // T*, state C^n (all members)
+    void* W;                   // T*, output of the x-solve
+    const MemberDev* mem;      // member table (global ids)
+    const int32_t* mids;       // member ids of this class
+    int32_t nmem;              // members in this class
+    int32_t nx, ny, nz;
+    int32_t P;                 // lanes per x-line (chunks)
+    int32_t rows_per_wave;     // x-lines per wavefront
+    int32_t waves;             // wavefronts per block (1, 2 or 4)
+    int32_t R;                 // x-lines per block (= waves * rows_per_wave)
+    int32_t bands_y;           // y-bands per (member, z) = ceil(ny / R)
+    int64_t nblocks;           // blocks of this launch
+    int32_t pitch;             // LDS row pitch (elements)
+    int32_t mode;
+    int32_t conv;              // energy convention
+    int32_t K;                 // cadence
+    int64_t max_samples;
+    double* partials;          // [nblocks][3]
+    uint32_t* done;            // block completion counter (self-resetting)
+    int64_t* step;             // step counter of this class
+    double* series;            // [member][max_samples][kSeriesSlots]
+    double* energy_now;        // [member][4]
+    int32_t* flags;            // [member] sticky non-finite flags
+};
+
+struct ColArgs {
+    const void* src;           // T*
+    void* dst;                 // T* (may equal src)
+    const MemberDev* mem;
+    const int32_t* mids;
+    int32_t axis;              // 1 = y, 2 = z
+    int32_t n;                 // line length
+    int64_t stride;            // element distance between line neighbours
+    int32_t nx;                // columns come in runs of nx consecutive elements
+    int64_t outer;             // element distance between runs
+    int64_t cols;              // columns per member
+    int32_t b;                 // columns per block (divides nx)
+    int32_t P;                 // chunks per column
+    int64_t nblocks;
+};
+
+// Kernel launchers (ch_kernels.hip).  prec: 0 = double, 1 = float.  They
+// return hipErrorInvalidValue for an uninstantiated chunk length.
+hipError_t launch_passA(int prec, int dim, int cx, const PassAArgs& a, size_t lds_bytes,
+                        hipStream_t s);
+hipError_t launch_col(int prec, int cy, const ColArgs& a, hipStream_t s);
+hipError_t launch_init_member(int prec, void* C, int64_t sites, uint64_t seed, double c0,
+                              double noise, hipStream_t s);
+hipError_t launch_reset(int64_t* steps, int nsteps, int64_t value, uint32_t* done, int ndone,
+                        int32_t* flags, int m, double* series, int64_t series_len,
+                        hipStream_t s);
+hipError_t launch_beta(const double* series, int64_t max_samples, int32_t member, int32_t K,
+                       int64_t ncur, double dt, double* out, int64_t J, hipStream_t s);
+
+bool passA_has(int dim, int cx);
+bool col_has(int prec, int cy);
+int passA_pad(int prec);       // LDS padding (elements) after every chunk
+
+}  // namespace chk

@@ -1,0 +1,843 @@
+// HIP kernels (gfx950) of the Cahn-Hilliard ensemble step.
+//
+// One step of the semi-implicit ADI scheme (paper: Section 4.1 and Appendix A;
+// the paper names the scheme but not its equations, so the form below is the
+// reading this library adopts):
+//
+//   RHS     = C + dt lap_h(C^3 - C) - 2 gamma dt sum_{d<e} D_d D_e C
+//   w       = (I + gamma dt D_x^2)^{-1} RHS            on every x-line
+//   C^{n+1} = (I + gamma dt D_z^2)^{-1} (I + gamma dt D_y^2)^{-1} w
+//
+// Kernels:
+//   passA_kernel  x-lines.  A block stages R x-lines of C plus halo rows (and,
+//                 in 3D, the neighbouring z-planes) in LDS, forms the RHS in
+//                 registers (lane = contiguous chunk of one line), solves the
+//                 periodic pentadiagonal system of every x-line and writes w.
+//                 On cadence steps it also forms the FP64 partial sums of F,
+//                 sum C and the dF/dt identity, and the last block to finish
+//                 reduces them per member in a fixed order.
+//   col_kernel    y- or z-lines.  A block owns b adjacent columns; lane
+//                 (column, chunk) holds a contiguous chunk of one line in
+//                 registers, loads are coalesced across columns.
+//
+// Line solve.  (I + rho [1,-4,6,-4,1]) is circulant with symbol
+// 1 + rho (z - 2 + 1/z)^2 = kappa Q(z) Q(1/z), Q(z) = (1 - p/z)(1 - conj(p)/z),
+// |p| < 1.  So the inverse is a causal second-order recursion followed by the
+// mirrored anti-causal one, each applied to the periodic sequence.  Every
+// chunk first runs the recursion from a zero state to get its end state
+// (a pair of values), the chunk end states are combined by a scan with the
+// chunk transfer matrix A^c (closing the ring with (I - A^n)^{-1}), and every
+// chunk then reruns the recursion from its true incoming state.  Work per
+// element and sweep: four two-term recursions and one scale.
+#include "ch_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace chk {
+
+// --------------------------------------------------------------------------
+// helpers
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
+{
+    // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous range of logical tiles so that neighbouring tiles (which share
+    // halo rows and planes) hit the same L2.  A bijection for any nb.
+    int64_t q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+template <typename T>
+struct LineCoef {
+    T a1, a2, ik;
+    T M[4];
+    T Mp[kMaxScanLevels][4];
+    T W[4];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_coef(LineCoef<T>& c, const AxisCoef& s, int levels)
+{
+    c.a1 = (T)s.a1;
+    c.a2 = (T)s.a2;
+    c.ik = (T)s.ikappa;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        c.M[i] = (T)s.M[i];
+        c.W[i] = (T)s.W[i];
+    }
+    for (int l = 0; l < levels && l < kMaxScanLevels; ++l)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c.Mp[l][i] = (T)s.Mp[l][i];
+}
+
+template <typename T>
+__device__ __forceinline__ void mv(const T* M, T& x0, T& x1)
+{
+    T y0 = M[0] * x0 + M[1] * x1;
+    T y1 = M[2] * x0 + M[3] * x1;
+    x0 = y0;
+    x1 = y1;
+}
+
+// causal recursion over a chunk from a zero state: end state (u_last, u_last-1)
+template <typename T, int CL>
+__device__ __forceinline__ void fwd_zero(const T (&v)[CL], T a1, T a2, T& e0, T& e1)
+{
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int k = 0; k < CL; ++k) {
+        T u = fma(a1, s0, fma(a2, s1, v[k]));
+        s1 = s0;
+        s0 = u;
+    }
+    e0 = s0;
+    e1 = s1;
+}
+
+template <typename T, int CL>
+__device__ __forceinline__ void fwd_true(T (&v)[CL], T a1, T a2, T s0, T s1)
+{
+#pragma unroll
+    for (int k = 0; k < CL; ++k) {
+        T u = fma(a1, s0, fma(a2, s1, v[k]));
+        s1 = s0;
+        s0 = u;
+        v[k] = u;
+    }
+}
+
+// anti-causal recursion from a zero state: state at the chunk start (v_0, v_1)
+template <typename T, int CL>
+__device__ __forceinline__ void bwd_zero(const T (&v)[CL], T a1, T a2, T& e0, T& e1)
+{
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int k = CL - 1; k >= 0; --k) {
+        T u = fma(a1, s0, fma(a2, s1, v[k]));
+        s1 = s0;
+        s0 = u;
+    }
+    e0 = s0;
+    e1 = s1;
+}
+
+template <typename T, int CL>
+__device__ __forceinline__ void bwd_true(T (&v)[CL], T a1, T a2, T s0, T s1, T ik)
+{
+#pragma unroll
+    for (int k = CL - 1; k >= 0; --k) {
+        T u = fma(a1, s0, fma(a2, s1, v[k]));
+        s1 = s0;
+        s0 = u;
+        v[k] = u * ik;
+    }
+}
+
+// Scan of chunk end states over the P lanes of one group inside a wavefront
+// (lanes gbase .. gbase+P-1, chunk j = lane - gbase).  On return (e0, e1) is
+// the true state entering chunk j.  All 64 lanes must call it.
+template <typename T>
+__device__ __forceinline__ void scan_fwd_wave(T& e0, T& e1, int j, int P, int gbase,
+                                              const LineCoef<T>& c)
+{
+    T x0 = e0, x1 = e1;
+    int s = 0;
+    for (int d = 1; d < P; d <<= 1, ++s) {
+        T y0 = __shfl_up(x0, d, 64);
+        T y1 = __shfl_up(x1, d, 64);
+        if (j >= d) {
+            mv(c.Mp[s], y0, y1);
+            x0 += y0;
+            x1 += y1;
+        }
+    }
+    T z0 = __shfl(x0, gbase + P - 1, 64);
+    T z1 = __shfl(x1, gbase + P - 1, 64);
+    T r0 = c.W[0] * z0 + c.W[1] * z1;  // state after the whole line = entering chunk 0
+    T r1 = c.W[2] * z0 + c.W[3] * z1;
+    T p0 = __shfl_up(x0, 1, 64);
+    T p1 = __shfl_up(x1, 1, 64);
+    if (j == 0) {
+        p0 = T(0);
+        p1 = T(0);
+    }
+    s = 0;
+    for (int d = 1; d < P; d <<= 1, ++s)
+        if (j & d) mv(c.Mp[s], r0, r1);
+    e0 = p0 + r0;
+    e1 = p1 + r1;
+}
+
+template <typename T>
+__device__ __forceinline__ void scan_bwd_wave(T& e0, T& e1, int j, int P, int gbase,
+                                              const LineCoef<T>& c)
+{
+    T x0 = e0, x1 = e1;
+    int s = 0;
+    for (int d = 1; d < P; d <<= 1, ++s) {
+        T y0 = __shfl_down(x0, d, 64);
+        T y1 = __shfl_down(x1, d, 64);
+        if (j + d < P) {
+            mv(c.Mp[s], y0, y1);
+            x0 += y0;
+            x1 += y1;
+        }
+    }
+    T z0 = __shfl(x0, gbase, 64);
+    T z1 = __shfl(x1, gbase, 64);
+    T r0 = c.W[0] * z0 + c.W[1] * z1;  // state at the line start = entering chunk P-1
+    T r1 = c.W[2] * z0 + c.W[3] * z1;
+    T p0 = __shfl_down(x0, 1, 64);
+    T p1 = __shfl_down(x1, 1, 64);
+    if (j == P - 1) {
+        p0 = T(0);
+        p1 = T(0);
+    }
+    int q = P - 1 - j;
+    s = 0;
+    for (int d = 1; d < P; d <<= 1, ++s)
+        if (q & d) mv(c.Mp[s], r0, r1);
+    e0 = p0 + r0;
+    e1 = p1 + r1;
+}
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+    using type = double2;
+    static constexpr int n = 2;
+};
+template <>
+struct Vec16<float> {
+    using type = float4;
+    static constexpr int n = 4;
+};
+
+template <typename T>
+__device__ __forceinline__ void vec_get(const typename Vec16<T>::type& v, T* out);
+template <>
+__device__ __forceinline__ void vec_get<double>(const double2& v, double* out)
+{
+    out[0] = v.x;
+    out[1] = v.y;
+}
+template <>
+__device__ __forceinline__ void vec_get<float>(const float4& v, float* out)
+{
+    out[0] = v.x;
+    out[1] = v.y;
+    out[2] = v.z;
+    out[3] = v.w;
+}
+template <typename T>
+__device__ __forceinline__ typename Vec16<T>::type vec_make(const T* in);
+template <>
+__device__ __forceinline__ double2 vec_make<double>(const double* in)
+{
+    return make_double2(in[0], in[1]);
+}
+template <>
+__device__ __forceinline__ float4 vec_make<float>(const float* in)
+{
+    return make_float4(in[0], in[1], in[2], in[3]);
+}
+
+template <typename T>
+struct PadOf;
+template <>
+struct PadOf<double> {
+    static constexpr int v = 1;
+};
+template <>
+struct PadOf<float> {
+    static constexpr int v = 1;
+};
+
+// --------------------------------------------------------------------------
+// pass A: RHS + diagnostics + x-line solves
+// --------------------------------------------------------------------------
+template <typename T, int DIM, int CX>
+__global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* sC = reinterpret_cast<T*>(lds_raw);
+    __shared__ double red[kPassAThreads / 64][3];
+    __shared__ int s_last;
+
+    constexpr int PADE = PadOf<T>::v;
+    constexpr int VEC = Vec16<T>::n;
+    using VT = typename Vec16<T>::type;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+
+    const int64_t blk = xcd_remap(blockIdx.x, a.nblocks);
+    const int64_t per_member = (int64_t)a.bands_y * nz;
+    const int mloc = (int)(blk / per_member);
+    const int64_t rem = blk - (int64_t)mloc * per_member;
+    const int z = (int)(rem / a.bands_y);
+    const int y0 = (int)(rem - (int64_t)z * a.bands_y) * a.R;
+    const int mid = a.mids[mloc];
+    const MemberDev& md = a.mem[mid];
+    const T* C = reinterpret_cast<const T*>(a.C) + md.off;
+    T* Wout = reinterpret_cast<T*>(a.W) + md.off;
+
+    const int64_t n = *a.step;
+    const int K = a.K;
+    bool needF = false, needG = false;
+    if (a.mode == MODE_STEP) {
+        needG = (n % K) == 0;
+        needF = needG || (n >= 1 && ((n - 1) % K) == 0) || (((n + 1) % K) == 0);
+    } else if (a.mode == MODE_DIAG) {
+        needF = needG = true;
+    }
+    const bool solve = (a.mode != MODE_DIAG);
+
+    // ---- stage C rows (with periodic halos) in LDS --------------------------
+    const int nthreads = blockDim.x;  // 64 * waves
+    const int rowsAlloc = a.R + 3;
+    const int pitch = a.pitch;
+    const int planeStride = rowsAlloc * pitch;
+    const int Ract = min(a.R, ny - y0);  // x-lines of this block inside the grid
+    const int nrows = Ract + (needG ? 3 : 2);
+    const int npl = (DIM == 3) ? (needG ? 4 : 3) : 1;
+    {
+        const int nvec = nx / VEC;
+        const int nrr = npl * nrows;
+        auto stage = [&](int rr, int xv) {
+            const int pl = rr / nrows, r = rr - pl * nrows;
+            const int zz = (DIM == 3) ? wrapi(z - 1 + pl, nz) : 0;
+            const int yy = wrapi(y0 - 1 + r, ny);
+            const T* src = C + ((int64_t)zz * ny + yy) * nx + xv * VEC;
+            T vals[VEC];
+            vec_get<T>(*reinterpret_cast<const VT*>(src), vals);
+            T* drow = sC + pl * planeStride + r * pitch;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const int x = xv * VEC + e;
+                int xx = x + kHalo;
+                drow[xx + (xx / CX) * PADE] = vals[e];
+                if (x >= nx - kHalo) {
+                    xx = x - nx + kHalo;
+                    drow[xx + (xx / CX) * PADE] = vals[e];
+                }
+                if (x < kHalo) {
+                    xx = x + nx + kHalo;
+                    drow[xx + (xx / CX) * PADE] = vals[e];
+                }
+            }
+        };
+        if (nvec >= nthreads) {
+            for (int rr = 0; rr < nrr; ++rr)
+                for (int xv = tid; xv < nvec; xv += nthreads) stage(rr, xv);
+        } else {
+            const int rpi = nthreads / nvec;
+            const int r0 = tid / nvec, xv = tid - r0 * nvec;
+            if (r0 < rpi)
+                for (int rr = r0; rr < nrr; rr += rpi) stage(rr, xv);
+        }
+    }
+    __syncthreads();
+
+    // ---- per-lane work: one chunk of CX elements of one x-line --------------
+    const int P = a.P;
+    const int g = lane / P;
+    const int j = lane - g * P;
+    const int r = wave * a.rows_per_wave + g;  // x-line within the block
+    const bool active = (g < a.rows_per_wave) && (r < Ract);
+    constexpr int PL0 = (DIM == 3) ? 1 : 0;
+    const T* cb = sC + PL0 * planeStride + (r + 1) * pitch + j * (CX + PADE);
+#define AT(dz, dy, m) cb[(dz) * planeStride + (dy) * pitch + (m) + ((m) / CX) * PADE]
+
+    const T ihx2 = (T)md.ih2[0], ihy2 = (T)md.ih2[1], ihz2 = (T)md.ih2[2];
+    const T dt = (T)md.dt, tg = (T)(2.0 * md.gamma * md.dt);
+    const T cxy = (T)(md.ih2[0] * md.ih2[1]);
+    const T cxz = (T)(md.ih2[0] * md.ih2[2]), cyz = (T)(md.ih2[1] * md.ih2[2]);
+
+    T v[CX];
+#pragma unroll
+    for (int k = 0; k < CX; ++k) v[k] = T(0);
+
+    double pF = 0.0, pS = 0.0, pG = 0.0;
+    if (active) {
+        if (solve) {
+#pragma unroll
+            for (int k = 0; k < CX; ++k) {
+                const int m0 = k + kHalo;
+                const T c = AT(0, 0, m0), cw = AT(0, 0, m0 - 1), ce = AT(0, 0, m0 + 1);
+                const T cn = AT(0, 1, m0), cs = AT(0, -1, m0);
+                const T Nc = c * c * c - c;
+                const T Nw = cw * cw * cw - cw, Ne = ce * ce * ce - ce;
+                const T Nn = cn * cn * cn - cn, Ns = cs * cs * cs - cs;
+                T lapN = (Ne - T(2) * Nc + Nw) * ihx2 + (Nn - T(2) * Nc + Ns) * ihy2;
+                const T dxx0 = ce - T(2) * c + cw;
+                const T dxxn = AT(0, 1, m0 + 1) - T(2) * cn + AT(0, 1, m0 - 1);
+                const T dxxs = AT(0, -1, m0 + 1) - T(2) * cs + AT(0, -1, m0 - 1);
+                T cross = (dxxn - T(2) * dxx0 + dxxs) * cxy;
+                if (DIM == 3) {
+                    const T cu = AT(1, 0, m0), cd = AT(-1, 0, m0);
+                    const T Nu = cu * cu * cu - cu, Nd = cd * cd * cd - cd;
+                    lapN += (Nu - T(2) * Nc + Nd) * ihz2;
+                    const T dxxu = AT(1, 0, m0 + 1) - T(2) * cu + AT(1, 0, m0 - 1);
+                    const T dxxd = AT(-1, 0, m0 + 1) - T(2) * cd + AT(-1, 0, m0 - 1);
+                    cross += (dxxu - T(2) * dxx0 + dxxd) * cxz;
+                    const T dyy0 = cn - T(2) * c + cs;
+                    const T dyyu = AT(1, 1, m0) - T(2) * cu + AT(1, -1, m0);
+                    const T dyyd = AT(-1, 1, m0) - T(2) * cd + AT(-1, -1, m0);
+                    cross += (dyyu - T(2) * dyy0 + dyyd) * cyz;
+                }
+                v[k] = c + dt * lapN - tg * cross;
+            }
+        }
+        if (needF) {
+            const double cbulk = a.conv ? 0.5 : 0.25;
+            const double hg = 0.5 * md.gamma;
+            const double dx2 = md.ih2[0], dy2 = md.ih2[1], dz2 = md.ih2[2];
+#pragma unroll
+            for (int k = 0; k < CX; ++k) {
+                const int m0 = k + kHalo;
+                const double c = (double)AT(0, 0, m0);
+                const double ex = (double)AT(0, 0, m0 + 1) - c;
+                const double ey = (double)AT(0, 1, m0) - c;
+                double gr = ex * ex * dx2 + ey * ey * dy2;
+                if (DIM == 3) {
+                    const double ez = (double)AT(1, 0, m0) - c;
+                    gr += ez * ez * dz2;
+                }
+                const double q = c * c - 1.0;
+                pF += cbulk * q * q + hg * gr;
+                pS += c;
+            }
+        }
+        if (needG) {
+            const double gam = md.gamma;
+            const double dx2 = md.ih2[0], dy2 = md.ih2[1], dz2 = md.ih2[2];
+            // chemical potential mu = C^3 - C - gamma lap_h C at (dz, dy, m)
+            auto MU = [&](int dz, int dy, int m) -> double {
+                const double u = (double)AT(dz, dy, m);
+                double l = ((double)AT(dz, dy, m + 1) - 2.0 * u + (double)AT(dz, dy, m - 1)) * dx2 +
+                           ((double)AT(dz, dy + 1, m) - 2.0 * u + (double)AT(dz, dy - 1, m)) * dy2;
+                if (DIM == 3)
+                    l += ((double)AT(dz + 1, dy, m) - 2.0 * u + (double)AT(dz - 1, dy, m)) * dz2;
+                return u * u * u - u - gam * l;
+            };
+#pragma unroll
+            for (int k = 0; k < CX; ++k) {
+                const int m0 = k + kHalo;
+                const double mu = MU(0, 0, m0);
+                const double gx = MU(0, 0, m0 + 1) - mu;
+                const double gy = MU(0, 1, m0) - mu;
+                double q = gx * gx * dx2 + gy * gy * dy2;
+                if (DIM == 3) {
+                    const double gz = MU(1, 0, m0) - mu;
+                    q += gz * gz * dz2;
+                }
+                pG += q;
+            }
+        }
+    }
+#undef AT
+
+    // ---- x-line solve (lanes of one line are contiguous in the wavefront) ---
+    if (solve) {
+        LineCoef<T> cf;
+        int levels = 0;
+        while ((1 << levels) < P) ++levels;
+        load_coef(cf, md.ax[0], levels);
+        const int gbase = g * P;
+        T e0, e1;
+        fwd_zero(v, cf.a1, cf.a2, e0, e1);
+        scan_fwd_wave(e0, e1, j, P, gbase, cf);
+        fwd_true(v, cf.a1, cf.a2, e0, e1);
+        bwd_zero(v, cf.a1, cf.a2, e0, e1);
+        scan_bwd_wave(e0, e1, j, P, gbase, cf);
+        bwd_true(v, cf.a1, cf.a2, e0, e1, cf.ik);
+    }
+
+    // ---- diagnostics partials -------------------------------------------------
+    if (needF) {
+        for (int off = 32; off > 0; off >>= 1) {
+            pF += __shfl_down(pF, off, 64);
+            pS += __shfl_down(pS, off, 64);
+            pG += __shfl_down(pG, off, 64);
+        }
+        if (lane == 0) {
+            red[wave][0] = pF;
+            red[wave][1] = pS;
+            red[wave][2] = pG;
+        }
+    }
+    __syncthreads();  // LDS stencil reads done; wave partials visible
+
+    // ---- write w through LDS (coalesced) -------------------------------------
+    if (solve) {
+        T* so = sC + (r + 1) * pitch + j * (CX + PADE);  // plane slot 0 is free now
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < CX; ++k) {
+                const int m = k + kHalo;
+                so[m + (m / CX) * PADE] = v[k];
+            }
+        }
+        __syncthreads();
+        const int nvec = nx / VEC;
+        const int tot = Ract * nvec;
+        for (int i = tid; i < tot; i += nthreads) {
+            const int rr = i / nvec, xv = i - rr * nvec;
+            const T* srow = sC + (rr + 1) * pitch;
+            T vals[VEC];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const int xx = xv * VEC + e + kHalo;
+                vals[e] = srow[xx + (xx / CX) * PADE];
+            }
+            *reinterpret_cast<VT*>(Wout + ((int64_t)z * ny + y0 + rr) * nx + xv * VEC) =
+                vec_make<T>(vals);
+        }
+    }
+
+    if (a.mode == MODE_TIMING) return;
+
+    // ---- block completion; the last block reduces per member -------------
+    if (tid == 0) {
+        if (needF) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int w = 0; w < nthreads / 64; ++w) {
+                s0 += red[w][0];
+                s1 += red[w][1];
+                s2 += red[w][2];
+            }
+            __hip_atomic_store(&a.partials[blk * 3 + 0], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.partials[blk * 3 + 1], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.partials[blk * 3 + 2], s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __threadfence();
+        const uint32_t prev =
+            __hip_atomic_fetch_add(a.done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (prev == (uint32_t)(a.nblocks - 1));
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+
+    if (needF) {
+        for (int ml = tid; ml < a.nmem; ml += nthreads) {
+            const int gm = a.mids[ml];
+            const MemberDev& mm = a.mem[gm];
+            // Neumaier-compensated sums over this member's blocks, in block order
+            double s[3] = {0.0, 0.0, 0.0}, cmp[3] = {0.0, 0.0, 0.0};
+            for (int64_t b = (int64_t)ml * per_member; b < (int64_t)(ml + 1) * per_member; ++b) {
+                for (int q = 0; q < 3; ++q) {
+                    const double x = __hip_atomic_load(&a.partials[b * 3 + q], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                    const double t = s[q] + x;
+                    cmp[q] += (fabs(s[q]) >= fabs(x)) ? (s[q] - t) + x : (x - t) + s[q];
+                    s[q] = t;
+                }
+            }
+            const double F = mm.vol * (s[0] + cmp[0]);
+            const double mC = (s[1] + cmp[1]) / (double)mm.sites;
+            const double G = -mm.vol * (s[2] + cmp[2]);
+            double* ser = a.series + (int64_t)gm * a.max_samples * kSeriesSlots;
+            const int64_t ms = a.max_samples;
+            if (n % K == 0 && n / K < ms) {
+                ser[(n / K) * kSeriesSlots + 1] = F;
+                if (needG) {
+                    ser[(n / K) * kSeriesSlots + 3] = mC;
+                    ser[(n / K) * kSeriesSlots + 4] = G;
+                }
+            }
+            if (n >= 1 && (n - 1) % K == 0 && (n - 1) / K < ms) ser[((n - 1) / K) * kSeriesSlots + 2] = F;
+            if ((n + 1) % K == 0 && (n + 1) / K < ms) ser[((n + 1) / K) * kSeriesSlots + 0] = F;
+            if (a.mode == MODE_DIAG) {
+                double* en = a.energy_now + (int64_t)gm * 4;
+                en[0] = F;
+                en[1] = mC;
+                en[2] = G;
+                en[3] = (double)n;
+            }
+            if (!isfinite(F)) a.flags[gm] = 1;
+        }
+    }
+    if (tid == 0) {
+        if (a.mode == MODE_STEP) *a.step = n + 1;
+        __hip_atomic_store(a.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// --------------------------------------------------------------------------
+// y- / z-line solves
+// --------------------------------------------------------------------------
+template <typename T, int CY>
+__global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int bP = a.b * a.P;
+    T* sE0 = reinterpret_cast<T*>(lds_raw);
+    T* sE1 = sE0 + bP;
+    T* sF0 = sE1 + bP;
+    T* sF1 = sF0 + bP;
+
+    const int tid = threadIdx.x;
+    const int j = tid / a.b;
+    const int c = tid - j * a.b;
+    const int P = a.P;
+    const int64_t blk = xcd_remap(blockIdx.x, a.nblocks);
+    const int64_t bpm = a.cols / a.b;
+    const int mloc = (int)(blk / bpm);
+    const int64_t col = (blk - (int64_t)mloc * bpm) * a.b + c;
+    const int64_t base = (col % a.nx) + (col / a.nx) * a.outer;
+    const MemberDev& md = a.mem[a.mids[mloc]];
+    const T* src = reinterpret_cast<const T*>(a.src) + md.off + base;
+    T* dst = reinterpret_cast<T*>(a.dst) + md.off + base;
+    const int64_t st = a.stride;
+
+    T v[CY];
+#pragma unroll
+    for (int k = 0; k < CY; ++k) v[k] = src[(int64_t)(j * CY + k) * st];
+
+    const AxisCoef& ac = md.ax[a.axis];
+    const T a1 = (T)ac.a1, a2 = (T)ac.a2, ik = (T)ac.ikappa;
+    T M[4], W[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        M[i] = (T)ac.M[i];
+        W[i] = (T)ac.W[i];
+    }
+
+    // causal recursion
+    T e0, e1;
+    fwd_zero(v, a1, a2, e0, e1);
+    sE0[j * a.b + c] = e0;
+    sE1[j * a.b + c] = e1;
+    __syncthreads();
+    if (j == 0) {
+        T z0 = T(0), z1 = T(0);
+        for (int q = 0; q < P; ++q) {
+            mv(M, z0, z1);
+            z0 += sE0[q * a.b + c];
+            z1 += sE1[q * a.b + c];
+        }
+        T s0 = W[0] * z0 + W[1] * z1, s1 = W[2] * z0 + W[3] * z1;
+        for (int q = 0; q < P; ++q) {
+            const T f0 = sE0[q * a.b + c], f1 = sE1[q * a.b + c];
+            sE0[q * a.b + c] = s0;
+            sE1[q * a.b + c] = s1;
+            mv(M, s0, s1);
+            s0 += f0;
+            s1 += f1;
+        }
+    }
+    __syncthreads();
+    fwd_true(v, a1, a2, sE0[j * a.b + c], sE1[j * a.b + c]);
+
+    // anti-causal recursion
+    bwd_zero(v, a1, a2, e0, e1);
+    sF0[j * a.b + c] = e0;
+    sF1[j * a.b + c] = e1;
+    __syncthreads();
+    if (j == P - 1) {
+        T z0 = T(0), z1 = T(0);
+        for (int q = P - 1; q >= 0; --q) {
+            mv(M, z0, z1);
+            z0 += sF0[q * a.b + c];
+            z1 += sF1[q * a.b + c];
+        }
+        T s0 = W[0] * z0 + W[1] * z1, s1 = W[2] * z0 + W[3] * z1;
+        for (int q = P - 1; q >= 0; --q) {
+            const T f0 = sF0[q * a.b + c], f1 = sF1[q * a.b + c];
+            sF0[q * a.b + c] = s0;
+            sF1[q * a.b + c] = s1;
+            mv(M, s0, s1);
+            s0 += f0;
+            s1 += f1;
+        }
+    }
+    __syncthreads();
+    bwd_true(v, a1, a2, sF0[j * a.b + c], sF1[j * a.b + c], ik);
+
+#pragma unroll
+    for (int k = 0; k < CY; ++k) dst[(int64_t)(j * CY + k) * st] = v[k];
+}
+
+// --------------------------------------------------------------------------
+// initial condition, resets, beta series
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k)
+{
+    // k-th output of SplitMix64 (Steele, Lea & Flood 2014)
+    uint64_t z = seed + k * 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+template <typename T>
+__global__ void init_kernel(T* C, int64_t sites, uint64_t seed, double c0, double noise)
+{
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < sites;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const double u = (double)(splitmix64_at(seed, (uint64_t)s + 1) >> 11) * 0x1.0p-53;
+        C[s] = (T)(c0 + noise * (2.0 * u - 1.0));
+    }
+}
+
+__global__ void reset_kernel(int64_t* steps, int nsteps, int64_t value, uint32_t* done, int ndone,
+                             int32_t* flags, int m, double* series, int64_t series_len)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t T = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = t; i < series_len; i += T) series[i] = __builtin_nan("");
+    for (int64_t i = t; i < nsteps; i += T) steps[i] = value;
+    for (int64_t i = t; i < ndone; i += T) done[i] = 0u;
+    for (int64_t i = t; i < m; i += T) flags[i] = 0;
+}
+
+// Sample j (n = jK): t, F, G_fd, G_id, beta, <C>.  G_fd is the central
+// difference of the recorded F where both neighbours exist, else one-sided.
+__global__ void beta_kernel(const double* series, int64_t max_samples, int32_t member, int32_t K,
+                            int64_t ncur, double dt, double* out, int64_t J)
+{
+    const double* ser = series + (int64_t)member * max_samples * kSeriesSlots;
+    for (int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; jj < J;
+         jj += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t n = jj * K;
+        const double Fm = ser[jj * kSeriesSlots + 0], F0 = ser[jj * kSeriesSlots + 1];
+        const double Fp = ser[jj * kSeriesSlots + 2];
+        const bool hasm = n >= 1 && !isnan(Fm);
+        const bool hasp = n + 1 <= ncur && !isnan(Fp);
+        double G;
+        if (hasm && hasp)
+            G = (Fp - Fm) / (2.0 * dt);
+        else if (hasp)
+            G = (Fp - F0) / dt;
+        else if (hasm)
+            G = (F0 - Fm) / dt;
+        else
+            G = __builtin_nan("");
+        const double t = (double)n * dt;
+        double* o = out + jj * 6;
+        o[0] = t;
+        o[1] = F0;
+        o[2] = G;
+        o[3] = ser[jj * kSeriesSlots + 4];
+        o[4] = (n == 0) ? 0.0 : -t * G / F0;
+        o[5] = ser[jj * kSeriesSlots + 3];
+    }
+}
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+template <typename T, int DIM, int CX>
+static hipError_t launchA(const PassAArgs& a, size_t lds, hipStream_t s)
+{
+    auto k = passA_kernel<T, DIM, CX>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k, dim3((unsigned)a.nblocks), dim3(64 * a.waves), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int DIM>
+static hipError_t launchA_cx(int cx, const PassAArgs& a, size_t lds, hipStream_t s)
+{
+    switch (cx) {
+    case 4: return launchA<T, DIM, 4>(a, lds, s);
+    case 8: return launchA<T, DIM, 8>(a, lds, s);
+    case 16: return launchA<T, DIM, 16>(a, lds, s);
+    case 32: return launchA<T, DIM, 32>(a, lds, s);
+    case 64: return launchA<T, DIM, 64>(a, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+bool passA_has(int dim, int cx)
+{
+    return (dim == 2 || dim == 3) && (cx == 4 || cx == 8 || cx == 16 || cx == 32 || cx == 64);
+}
+
+int passA_pad(int prec) { return prec == 0 ? PadOf<double>::v : PadOf<float>::v; }
+
+hipError_t launch_passA(int prec, int dim, int cx, const PassAArgs& a, size_t lds, hipStream_t s)
+{
+    if (a.nblocks <= 0) return hipSuccess;
+    if (prec == 0) return dim == 2 ? launchA_cx<double, 2>(cx, a, lds, s) : launchA_cx<double, 3>(cx, a, lds, s);
+    return dim == 2 ? launchA_cx<float, 2>(cx, a, lds, s) : launchA_cx<float, 3>(cx, a, lds, s);
+}
+
+template <typename T, int CY>
+static hipError_t launchC(const ColArgs& a, hipStream_t s)
+{
+    const size_t lds = (size_t)4 * a.b * a.P * sizeof(T);
+    hipLaunchKernelGGL((col_kernel<T, CY>), dim3((unsigned)a.nblocks), dim3(a.b * a.P), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launchC_cy(int cy, const ColArgs& a, hipStream_t s)
+{
+    switch (cy) {
+    case 4: return launchC<T, 4>(a, s);
+    case 8: return launchC<T, 8>(a, s);
+    case 16: return launchC<T, 16>(a, s);
+    case 32: return launchC<T, 32>(a, s);
+    case 64: return launchC<T, 64>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+bool col_has(int prec, int cy)
+{
+    if (prec == 0) return cy == 4 || cy == 8 || cy == 16 || cy == 32;
+    return cy == 4 || cy == 8 || cy == 16 || cy == 32 || cy == 64;
+}
+
+hipError_t launch_col(int prec, int cy, const ColArgs& a, hipStream_t s)
+{
+    if (a.nblocks <= 0) return hipSuccess;
+    if (!col_has(prec, cy)) return hipErrorInvalidValue;
+    return prec == 0 ? launchC_cy<double>(cy, a, s) : launchC_cy<float>(cy, a, s);
+}
+
+hipError_t launch_init_member(int prec, void* C, int64_t sites, uint64_t seed, double c0,
+                              double noise, hipStream_t s)
+{
+    const int64_t blocks = std::min<int64_t>((sites + 255) / 256, 65536);
+    if (prec == 0)
+        hipLaunchKernelGGL(init_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           reinterpret_cast<double*>(C), sites, seed, c0, noise);
+    else
+        hipLaunchKernelGGL(init_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           reinterpret_cast<float*>(C), sites, seed, c0, noise);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(int64_t* steps, int nsteps, int64_t value, uint32_t* done, int ndone,
+                        int32_t* flags, int m, double* series, int64_t series_len, hipStream_t s)
+{
+    int64_t big = std::max<int64_t>(series_len, std::max<int64_t>(m, std::max(nsteps, ndone)));
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((big + 255) / 256, 4096));
+    hipLaunchKernelGGL(reset_kernel, dim3((unsigned)blocks), dim3(256), 0, s, steps, nsteps, value,
+                       done, ndone, flags, m, series, series_len);
+    return hipGetLastError();
+}
+
+hipError_t launch_beta(const double* series, int64_t max_samples, int32_t member, int32_t K,
+                       int64_t ncur, double dt, double* out, int64_t J, hipStream_t s)
+{
+    if (J <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((J + 255) / 256, 1024);
+    hipLaunchKernelGGL(beta_kernel, dim3((unsigned)blocks), dim3(256), 0, s, series, max_samples,
+                       member, K, ncur, dt, out, J);
+    return hipGetLastError();
+}
+
+}  // namespace chk
