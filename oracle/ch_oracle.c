@@ -33,8 +33,11 @@
  * Sums are exactly rounded (Shewchuk's non-overlapping partials).
  *
  * The periodic line solve uses the Sherman-Morrison-Woodbury formula on top of
- * a banded LU factorisation of the non-periodic pentadiagonal part: a direct
- * method unrelated to whatever the GPU uses.
+ * a banded LU factorisation of the non-periodic pentadiagonal part (a direct
+ * method unrelated to whatever the GPU uses).  The line mean passes through
+ * the solve exactly (constants are fixed points of the operator, which is what
+ * conserves <C>), and one residual-correction step restores the digits the
+ * Woodbury cancellation loses at large gamma dt / h^4.
  *
  * Initial condition: C = c0 + noise (2u - 1), where u is built from the
  * (site+1)-th output of the SplitMix64 generator (Steele, Lea & Flood 2014)
@@ -365,8 +368,10 @@ static void penta_free(penta *q)
     free(q->Z);
 }
 
-/* y = A^{-1} f, y may alias f; tmp has room for n doubles */
-static void penta_solve(const penta *q, const double *f, double *y, double *tmp)
+/* y = A^{-1} f by the Woodbury formula: A = B + P K P^T, so
+ * A^{-1} f = B^{-1} f - Z (I + K P^T Z)^{-1} K P^T B^{-1} f with Z = B^{-1} P.
+ * tmp has room for n doubles; y must not alias f. */
+static void woodbury(const penta *q, const double *f, double *y, double *tmp)
 {
     int64_t n = q->n;
     int64_t idx[4] = {0, 1, n - 2, n - 1};
@@ -397,6 +402,30 @@ static void penta_solve(const penta *q, const double *f, double *y, double *tmp)
                          q->Z[3 * n + i] * t[3]);
 }
 
+/* y = A^{-1} f, y may alias f; work has room for 3n doubles.
+ * A maps constants to themselves (A 1 = 1: the line solve conserves the
+ * mean), so the mean of f passes through exactly and only the fluctuation
+ * g = f - mean(f) goes through Woodbury, followed by one step of residual
+ * correction with the exact stencil (the Woodbury formula on the non-periodic
+ * band loses a few digits to cancellation when rho is large). */
+static void penta_solve(const penta *q, const double *f, double *y, double *work)
+{
+    int64_t n = q->n;
+    double rho = q->rho;
+    double *g = work, *d = work + n, *tmp = work + 2 * n;
+    double mean = orc_exact_sum(f, n) / (double)n;
+    for (int64_t i = 0; i < n; i++) g[i] = f[i] - mean;
+    woodbury(q, g, d, tmp); /* d = A^{-1} g (first pass) */
+    for (int64_t i = 0; i < n; i++) {
+        int64_t im2 = (i - 2 + n) % n, im1 = (i - 1 + n) % n;
+        int64_t ip1 = (i + 1) % n, ip2 = (i + 2) % n;
+        double Ad = d[i] + rho * (d[im2] - 4.0 * d[im1] + 6.0 * d[i] - 4.0 * d[ip1] + d[ip2]);
+        g[i] = g[i] - Ad; /* residual */
+    }
+    woodbury(q, g, y, tmp); /* correction */
+    for (int64_t i = 0; i < n; i++) y[i] = mean + (d[i] + y[i]);
+}
+
 /* Public single-line solve, for the pins. Returns 0 on success. */
 int orc_cyclic_penta_solve(int64_t n, double rho, const double *f, double *y)
 {
@@ -406,9 +435,9 @@ int orc_cyclic_penta_solve(int64_t n, double rho, const double *f, double *y)
         penta_free(&q);
         return -2;
     }
-    double *tmp = (double *)malloc(sizeof(double) * n);
-    penta_solve(&q, f, y, tmp);
-    free(tmp);
+    double *work = (double *)malloc(sizeof(double) * 3 * n);
+    penta_solve(&q, f, y, work);
+    free(work);
     penta_free(&q);
     return 0;
 }
@@ -429,7 +458,7 @@ static int sweep(const grid *g, int d, double gamma, double dt, double *u)
 #pragma omp parallel
     {
         double *line = (double *)malloc(sizeof(double) * n);
-        double *tmp = (double *)malloc(sizeof(double) * n);
+        double *tmp = (double *)malloc(sizeof(double) * 3 * n);
 #pragma omp for schedule(static)
         for (int64_t l = 0; l < nlines; l++) {
             int64_t base = (l % lo) + (l / lo) * hi;

@@ -56,7 +56,7 @@ struct ClassPlan {
 };
 
 struct Layout {
-    size_t off_mem = 0, off_C = 0, off_W = 0, off_steps = 0, off_done = 0, off_flags = 0;
+    size_t off_mem = 0, off_C = 0, off_W = 0, off_steps = 0, off_flags = 0;
     size_t off_series = 0, off_energy = 0, off_beta = 0, total = 0;
     int64_t total_elems = 0;
     std::vector<int64_t> moff;  // element offset per member
@@ -330,8 +330,6 @@ void layout(const ch_member_desc* members, int32_t m, int prec, int64_t max_samp
     }
     L.off_steps = o;
     o = align_up(o + sizeof(int64_t) * classes.size());
-    L.off_done = o;
-    o = align_up(o + sizeof(uint32_t) * classes.size());
     L.off_flags = o;
     o = align_up(o + sizeof(int32_t) * m);
     L.off_series = o;
@@ -368,7 +366,6 @@ struct ch_ctx {
     void* d_C() { return ws + L.off_C; }
     void* d_W() { return ws + L.off_W; }
     int64_t* d_steps() { return reinterpret_cast<int64_t*>(ws + L.off_steps); }
-    uint32_t* d_done() { return reinterpret_cast<uint32_t*>(ws + L.off_done); }
     int32_t* d_flags() { return reinterpret_cast<int32_t*>(ws + L.off_flags); }
     double* d_series() { return reinterpret_cast<double*>(ws + L.off_series); }
     double* d_energy() { return reinterpret_cast<double*>(ws + L.off_energy); }
@@ -462,17 +459,32 @@ PassAArgs passA_args(ch_ctx* ctx, int ci, int mode)
     a.mode = mode;
     a.conv = ctx->conv;
     a.K = ctx->K;
-    a.max_samples = ctx->max_samples;
-    a.partials = reinterpret_cast<double*>(ctx->ws + c.off_partials);
-    a.done = ctx->d_done() + ci;
     a.step = ctx->d_steps() + ci;
-    a.series = ctx->d_series();
-    a.energy_now = ctx->d_energy();
-    a.flags = ctx->d_flags();
+    a.partials = reinterpret_cast<double*>(ctx->ws + c.off_partials);
     return a;
 }
 
-ColArgs col_args(ch_ctx* ctx, int ci, int axis, const void* src, void* dst)
+FinArgs fin_args(ch_ctx* ctx, int ci, int mode)
+{
+    ClassPlan& c = ctx->classes[ci];
+    FinArgs f{};
+    f.enabled = 1;
+    f.mode = mode;
+    f.mem = ctx->d_mem();
+    f.mids = reinterpret_cast<const int32_t*>(ctx->ws + c.off_mids);
+    f.nmem = (int32_t)c.members.size();
+    f.K = ctx->K;
+    f.blocks_per_member = (int64_t)c.nz * c.bands;
+    f.partials = reinterpret_cast<const double*>(ctx->ws + c.off_partials);
+    f.max_samples = ctx->max_samples;
+    f.step = ctx->d_steps() + ci;
+    f.series = ctx->d_series();
+    f.energy_now = ctx->d_energy();
+    f.flags = ctx->d_flags();
+    return f;
+}
+
+ColArgs col_args(ch_ctx* ctx, int ci, int axis, const void* src, void* dst, bool closes_step)
 {
     ClassPlan& c = ctx->classes[ci];
     const ColPlan& p = c.col[axis];
@@ -490,6 +502,7 @@ ColArgs col_args(ch_ctx* ctx, int ci, int axis, const void* src, void* dst)
     a.b = p.b;
     a.P = p.P;
     a.nblocks = p.nblocks;
+    if (closes_step) a.fin = fin_args(ctx, ci, MODE_STEP);
     return a;
 }
 
@@ -506,8 +519,9 @@ hipError_t launch_cols(ch_ctx* ctx, int ci, int axis)
     ClassPlan& c = ctx->classes[ci];
     void* W = ctx->d_W();
     void* C = ctx->d_C();
-    void* dst = (axis == c.dim - 1) ? C : W;
-    return launch_col(ctx->prec, c.col[axis].cy, col_args(ctx, ci, axis, W, dst), ctx->stream);
+    const bool last = (axis == c.dim - 1);
+    return launch_col(ctx->prec, c.col[axis].cy, col_args(ctx, ci, axis, W, last ? C : W, last),
+                      ctx->stream);
 }
 
 hipError_t enqueue_step(ch_ctx* ctx)
@@ -526,8 +540,10 @@ hipError_t enqueue_step(ch_ctx* ctx)
 hipError_t enqueue_diag(ch_ctx* ctx)
 {
     hipError_t e;
-    for (int ci = 0; ci < (int)ctx->classes.size(); ++ci)
+    for (int ci = 0; ci < (int)ctx->classes.size(); ++ci) {
         if ((e = launch_A(ctx, ci, MODE_DIAG)) != hipSuccess) return e;
+        if ((e = launch_fin(fin_args(ctx, ci, MODE_DIAG), ctx->stream)) != hipSuccess) return e;
+    }
     return hipSuccess;
 }
 
@@ -702,9 +718,8 @@ ch_status ch_create(const ch_member_desc* members, int32_t m, ch_precision prec,
         if (e != hipSuccess) break;
     }
     if (e == hipSuccess)
-        e = launch_reset(ctx->d_steps(), (int)ctx->classes.size(), 0, ctx->d_done(),
-                         (int)ctx->classes.size(), ctx->d_flags(), m, ctx->d_series(),
-                         (int64_t)kSeriesSlots * m * max_samples, ctx->stream);
+        e = launch_reset(ctx->d_steps(), (int)ctx->classes.size(), 0, ctx->d_flags(), m,
+                         ctx->d_series(), (int64_t)kSeriesSlots * m * max_samples, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         delete ctx;
@@ -729,9 +744,9 @@ ch_status ch_init_random(ch_ctx* ctx)
                                        static_cast<char*>(ctx->d_C()) + ctx->L.moff[i] * elem_size(ctx->prec),
                                        ctx->mem[i].sites, d.seed, d.c0, d.noise, ctx->stream));
     }
-    HIPCHK(ctx, launch_reset(ctx->d_steps(), (int)ctx->classes.size(), 0, ctx->d_done(),
-                             (int)ctx->classes.size(), ctx->d_flags(), m, ctx->d_series(),
-                             (int64_t)kSeriesSlots * m * ctx->max_samples, ctx->stream));
+    HIPCHK(ctx, launch_reset(ctx->d_steps(), (int)ctx->classes.size(), 0, ctx->d_flags(), m,
+                             ctx->d_series(), (int64_t)kSeriesSlots * m * ctx->max_samples,
+                             ctx->stream));
     ctx->step = 0;
     return CH_OK;
 }
@@ -792,9 +807,9 @@ ch_status ch_set_step(ch_ctx* ctx, int64_t n)
     if (n < 0) return fail(ctx, CH_EINVAL, "step must be >= 0");
     if (n / ctx->K >= ctx->max_samples) return fail(ctx, CH_ESTATE, "step beyond the sample capacity");
     const int m = (int)ctx->desc.size();
-    HIPCHK(ctx, launch_reset(ctx->d_steps(), (int)ctx->classes.size(), n, ctx->d_done(),
-                             (int)ctx->classes.size(), ctx->d_flags(), 0, ctx->d_series(),
-                             (int64_t)kSeriesSlots * m * ctx->max_samples, ctx->stream));
+    HIPCHK(ctx, launch_reset(ctx->d_steps(), (int)ctx->classes.size(), n, ctx->d_flags(), 0,
+                             ctx->d_series(), (int64_t)kSeriesSlots * m * ctx->max_samples,
+                             ctx->stream));
     ctx->step = n;
     return CH_OK;
 }
@@ -1034,7 +1049,8 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
                     void* W = ctx->d_W();
                     err = time_it(
                         [&] {
-                            return launch_col(ctx->prec, cy, col_args(ctx, ci, axis, W, W), ctx->stream);
+                            return launch_col(ctx->prec, cy, col_args(ctx, ci, axis, W, W, false),
+                                              ctx->stream);
                         },
                         ms);
                     if (err != hipSuccess) break;

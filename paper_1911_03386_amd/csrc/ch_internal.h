@@ -8,6 +8,7 @@
 namespace chk {
 
 constexpr int kMaxScanLevels = 7;  // (A^c)^(2^s), s < 7: enough for P <= 128 chunks
+constexpr int kWaveScanLevels = 6; // lanes of one line inside a wavefront: P <= 64
 constexpr int kSeriesSlots = 5;    // F(jK-1), F(jK), F(jK+1), <C>(jK), G_id(jK)
 constexpr int kPassAThreads = 256; // 4 wavefronts
 constexpr int kColMaxThreads = 512;
@@ -40,6 +41,26 @@ struct MemberDev {
 // Step kernel modes.
 enum : int { MODE_STEP = 0, MODE_DIAG = 1, MODE_TIMING = 2 };
 
+// Per-member reduction of the pass-A partial sums (F, sum C, sum |grad mu|^2)
+// into the sample series; run by block 0 of the last sweep of a step, or by
+// a one-block kernel after a diagnostics-only pass A.
+struct FinArgs {
+    int32_t enabled;           // 0: nothing to do
+    int32_t mode;              // MODE_STEP: record what step n needs, then n -> n+1
+                               // MODE_DIAG: record everything, keep n
+    const MemberDev* mem;
+    const int32_t* mids;       // member ids of the class
+    int32_t nmem;
+    int32_t K;                 // cadence
+    int64_t blocks_per_member; // pass-A blocks (= partial triples) per member
+    const double* partials;    // [member][blocks_per_member][3]
+    int64_t max_samples;
+    int64_t* step;             // step counter of the class
+    double* series;            // [member][max_samples][kSeriesSlots]
+    double* energy_now;        // [member][4]
+    int32_t* flags;            // [member] sticky non-finite flags
+};
+
 struct PassAArgs {
     const void* C;             // T*, state C^n (all members)
     void* W;                   // T*, output of the x-solve
@@ -57,13 +78,8 @@ struct PassAArgs {
     int32_t mode;
     int32_t conv;              // energy convention
     int32_t K;                 // cadence
-    int64_t max_samples;
+    const int64_t* step;       // step counter of this class (read only)
     double* partials;          // [nblocks][3]
-    uint32_t* done;            // block completion counter (self-resetting)
-    int64_t* step;             // step counter of this class
-    double* series;            // [member][max_samples][kSeriesSlots]
-    double* energy_now;        // [member][4]
-    int32_t* flags;            // [member] sticky non-finite flags
 };
 
 struct ColArgs {
@@ -80,6 +96,7 @@ struct ColArgs {
     int32_t b;                 // columns per block (divides nx)
     int32_t P;                 // chunks per column
     int64_t nblocks;
+    FinArgs fin;               // enabled on the last sweep of a step
 };
 
 // Kernel launchers (ch_kernels.hip).  prec: 0 = double, 1 = float.  They
@@ -89,9 +106,9 @@ hipError_t launch_passA(int prec, int dim, int cx, const PassAArgs& a, size_t ld
 hipError_t launch_col(int prec, int cy, const ColArgs& a, hipStream_t s);
 hipError_t launch_init_member(int prec, void* C, int64_t sites, uint64_t seed, double c0,
                               double noise, hipStream_t s);
-hipError_t launch_reset(int64_t* steps, int nsteps, int64_t value, uint32_t* done, int ndone,
-                        int32_t* flags, int m, double* series, int64_t series_len,
-                        hipStream_t s);
+hipError_t launch_reset(int64_t* steps, int nsteps, int64_t value, int32_t* flags, int m,
+                        double* series, int64_t series_len, hipStream_t s);
+hipError_t launch_fin(const FinArgs& f, hipStream_t s);
 hipError_t launch_beta(const double* series, int64_t max_samples, int32_t member, int32_t K,
                        int64_t ncur, double dt, double* out, int64_t J, hipStream_t s);
 

@@ -34,6 +34,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 namespace chk {
 
 // --------------------------------------------------------------------------
@@ -59,7 +61,7 @@ struct LineCoef {
 };
 
 template <typename T>
-__device__ __forceinline__ void load_coef(LineCoef<T>& c, const AxisCoef& s, int levels)
+__device__ __forceinline__ void load_coef(LineCoef<T>& c, const AxisCoef& s, int P)
 {
     c.a1 = (T)s.a1;
     c.a2 = (T)s.a2;
@@ -69,9 +71,11 @@ __device__ __forceinline__ void load_coef(LineCoef<T>& c, const AxisCoef& s, int
         c.M[i] = (T)s.M[i];
         c.W[i] = (T)s.W[i];
     }
-    for (int l = 0; l < levels && l < kMaxScanLevels; ++l)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) c.Mp[l][i] = (T)s.Mp[l][i];
+    for (int l = 0; l < kWaveScanLevels; ++l)
+        if ((1 << l) < P)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) c.Mp[l][i] = (T)s.Mp[l][i];
 }
 
 template <typename T>
@@ -139,20 +143,23 @@ __device__ __forceinline__ void bwd_true(T (&v)[CL], T a1, T a2, T s0, T s1, T i
 
 // Scan of chunk end states over the P lanes of one group inside a wavefront
 // (lanes gbase .. gbase+P-1, chunk j = lane - gbase).  On return (e0, e1) is
-// the true state entering chunk j.  All 64 lanes must call it.
+// the true state entering chunk j.  All 64 lanes must call it (P is uniform).
 template <typename T>
 __device__ __forceinline__ void scan_fwd_wave(T& e0, T& e1, int j, int P, int gbase,
                                               const LineCoef<T>& c)
 {
     T x0 = e0, x1 = e1;
-    int s = 0;
-    for (int d = 1; d < P; d <<= 1, ++s) {
-        T y0 = __shfl_up(x0, d, 64);
-        T y1 = __shfl_up(x1, d, 64);
-        if (j >= d) {
-            mv(c.Mp[s], y0, y1);
-            x0 += y0;
-            x1 += y1;
+#pragma unroll
+    for (int s = 0; s < kWaveScanLevels; ++s) {
+        const int d = 1 << s;
+        if (d < P) {
+            T y0 = __shfl_up(x0, d, 64);
+            T y1 = __shfl_up(x1, d, 64);
+            if (j >= d) {
+                mv(c.Mp[s], y0, y1);
+                x0 += y0;
+                x1 += y1;
+            }
         }
     }
     T z0 = __shfl(x0, gbase + P - 1, 64);
@@ -165,9 +172,9 @@ __device__ __forceinline__ void scan_fwd_wave(T& e0, T& e1, int j, int P, int gb
         p0 = T(0);
         p1 = T(0);
     }
-    s = 0;
-    for (int d = 1; d < P; d <<= 1, ++s)
-        if (j & d) mv(c.Mp[s], r0, r1);
+#pragma unroll
+    for (int s = 0; s < kWaveScanLevels; ++s)
+        if (((1 << s) < P) && (j & (1 << s))) mv(c.Mp[s], r0, r1);
     e0 = p0 + r0;
     e1 = p1 + r1;
 }
@@ -177,14 +184,17 @@ __device__ __forceinline__ void scan_bwd_wave(T& e0, T& e1, int j, int P, int gb
                                               const LineCoef<T>& c)
 {
     T x0 = e0, x1 = e1;
-    int s = 0;
-    for (int d = 1; d < P; d <<= 1, ++s) {
-        T y0 = __shfl_down(x0, d, 64);
-        T y1 = __shfl_down(x1, d, 64);
-        if (j + d < P) {
-            mv(c.Mp[s], y0, y1);
-            x0 += y0;
-            x1 += y1;
+#pragma unroll
+    for (int s = 0; s < kWaveScanLevels; ++s) {
+        const int d = 1 << s;
+        if (d < P) {
+            T y0 = __shfl_down(x0, d, 64);
+            T y1 = __shfl_down(x1, d, 64);
+            if (j + d < P) {
+                mv(c.Mp[s], y0, y1);
+                x0 += y0;
+                x1 += y1;
+            }
         }
     }
     T z0 = __shfl(x0, gbase, 64);
@@ -197,13 +207,70 @@ __device__ __forceinline__ void scan_bwd_wave(T& e0, T& e1, int j, int P, int gb
         p0 = T(0);
         p1 = T(0);
     }
-    int q = P - 1 - j;
-    s = 0;
-    for (int d = 1; d < P; d <<= 1, ++s)
-        if (q & d) mv(c.Mp[s], r0, r1);
+    const int q = P - 1 - j;
+#pragma unroll
+    for (int s = 0; s < kWaveScanLevels; ++s)
+        if (((1 << s) < P) && (q & (1 << s))) mv(c.Mp[s], r0, r1);
     e0 = p0 + r0;
     e1 = p1 + r1;
 }
+
+// Per-member reduction of the pass-A partials, in block order with Neumaier
+// compensation (deterministic), into the series; MODE_STEP then advances the
+// step counter.  Called by every thread of one block.
+__device__ void finalize(const FinArgs& f, int tid, int nthreads)
+{
+    const int64_t n = *f.step;
+    const int K = f.K;
+    bool needF = true, needG = true;
+    if (f.mode == MODE_STEP) {
+        needG = (n % K) == 0;
+        needF = needG || (n >= 1 && ((n - 1) % K) == 0) || (((n + 1) % K) == 0);
+    }
+    if (needF) {
+        for (int ml = tid; ml < f.nmem; ml += nthreads) {
+            const int gm = f.mids[ml];
+            const MemberDev& mm = f.mem[gm];
+            double s[3] = {0.0, 0.0, 0.0}, cmp[3] = {0.0, 0.0, 0.0};
+            const double* pp = f.partials + (int64_t)ml * f.blocks_per_member * 3;
+            for (int64_t b = 0; b < f.blocks_per_member; ++b) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const double x = pp[b * 3 + q];
+                    const double t = s[q] + x;
+                    cmp[q] += (fabs(s[q]) >= fabs(x)) ? (s[q] - t) + x : (x - t) + s[q];
+                    s[q] = t;
+                }
+            }
+            const double F = mm.vol * (s[0] + cmp[0]);
+            const double mC = (s[1] + cmp[1]) / (double)mm.sites;
+            const double G = -mm.vol * (s[2] + cmp[2]);
+            double* ser = f.series + (int64_t)gm * f.max_samples * kSeriesSlots;
+            const int64_t ms = f.max_samples;
+            if (n % K == 0 && n / K < ms) {
+                ser[(n / K) * kSeriesSlots + 1] = F;
+                if (needG) {
+                    ser[(n / K) * kSeriesSlots + 3] = mC;
+                    ser[(n / K) * kSeriesSlots + 4] = G;
+                }
+            }
+            if (n >= 1 && (n - 1) % K == 0 && (n - 1) / K < ms) ser[((n - 1) / K) * kSeriesSlots + 2] = F;
+            if ((n + 1) % K == 0 && (n + 1) / K < ms) ser[((n + 1) / K) * kSeriesSlots + 0] = F;
+            if (f.mode == MODE_DIAG) {
+                double* en = f.energy_now + (int64_t)gm * 4;
+                en[0] = F;
+                en[1] = mC;
+                en[2] = G;
+                en[3] = (double)n;
+            }
+            if (!isfinite(F)) f.flags[gm] = 1;
+        }
+    }
+    __syncthreads();  // every thread has read n
+    if (tid == 0 && f.mode == MODE_STEP) *f.step = n + 1;
+}
+
+__global__ void fin_kernel(FinArgs f) { finalize(f, threadIdx.x, blockDim.x); }
 
 template <typename T>
 struct Vec16;
@@ -267,7 +334,6 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* sC = reinterpret_cast<T*>(lds_raw);
     __shared__ double red[kPassAThreads / 64][3];
-    __shared__ int s_last;
 
     constexpr int PADE = PadOf<T>::v;
     constexpr int VEC = Vec16<T>::n;
@@ -445,9 +511,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     // ---- x-line solve (lanes of one line are contiguous in the wavefront) ---
     if (solve) {
         LineCoef<T> cf;
-        int levels = 0;
-        while ((1 << levels) < P) ++levels;
-        load_coef(cf, md.ax[0], levels);
+        load_coef(cf, md.ax[0], P);
         const int gbase = g * P;
         T e0, e1;
         fwd_zero(v, cf.a1, cf.a2, e0, e1);
@@ -500,72 +564,17 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
         }
     }
 
-    if (a.mode == MODE_TIMING) return;
-
-    // ---- block completion; the last block reduces per member -------------
-    if (tid == 0) {
-        if (needF) {
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-            for (int w = 0; w < nthreads / 64; ++w) {
-                s0 += red[w][0];
-                s1 += red[w][1];
-                s2 += red[w][2];
-            }
-            __hip_atomic_store(&a.partials[blk * 3 + 0], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&a.partials[blk * 3 + 1], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&a.partials[blk * 3 + 2], s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // ---- block partials of F, sum C, sum |grad mu|^2 (reduced by finalize) ----
+    if (needF && tid == 0) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int w = 0; w < nthreads / 64; ++w) {
+            s0 += red[w][0];
+            s1 += red[w][1];
+            s2 += red[w][2];
         }
-        __threadfence();
-        const uint32_t prev =
-            __hip_atomic_fetch_add(a.done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == (uint32_t)(a.nblocks - 1));
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-
-    if (needF) {
-        for (int ml = tid; ml < a.nmem; ml += nthreads) {
-            const int gm = a.mids[ml];
-            const MemberDev& mm = a.mem[gm];
-            // Neumaier-compensated sums over this member's blocks, in block order
-            double s[3] = {0.0, 0.0, 0.0}, cmp[3] = {0.0, 0.0, 0.0};
-            for (int64_t b = (int64_t)ml * per_member; b < (int64_t)(ml + 1) * per_member; ++b) {
-                for (int q = 0; q < 3; ++q) {
-                    const double x = __hip_atomic_load(&a.partials[b * 3 + q], __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-                    const double t = s[q] + x;
-                    cmp[q] += (fabs(s[q]) >= fabs(x)) ? (s[q] - t) + x : (x - t) + s[q];
-                    s[q] = t;
-                }
-            }
-            const double F = mm.vol * (s[0] + cmp[0]);
-            const double mC = (s[1] + cmp[1]) / (double)mm.sites;
-            const double G = -mm.vol * (s[2] + cmp[2]);
-            double* ser = a.series + (int64_t)gm * a.max_samples * kSeriesSlots;
-            const int64_t ms = a.max_samples;
-            if (n % K == 0 && n / K < ms) {
-                ser[(n / K) * kSeriesSlots + 1] = F;
-                if (needG) {
-                    ser[(n / K) * kSeriesSlots + 3] = mC;
-                    ser[(n / K) * kSeriesSlots + 4] = G;
-                }
-            }
-            if (n >= 1 && (n - 1) % K == 0 && (n - 1) / K < ms) ser[((n - 1) / K) * kSeriesSlots + 2] = F;
-            if ((n + 1) % K == 0 && (n + 1) / K < ms) ser[((n + 1) / K) * kSeriesSlots + 0] = F;
-            if (a.mode == MODE_DIAG) {
-                double* en = a.energy_now + (int64_t)gm * 4;
-                en[0] = F;
-                en[1] = mC;
-                en[2] = G;
-                en[3] = (double)n;
-            }
-            if (!isfinite(F)) a.flags[gm] = 1;
-        }
-    }
-    if (tid == 0) {
-        if (a.mode == MODE_STEP) *a.step = n + 1;
-        __hip_atomic_store(a.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a.partials[blk * 3 + 0] = s0;
+        a.partials[blk * 3 + 1] = s1;
+        a.partials[blk * 3 + 2] = s2;
     }
 }
 
@@ -662,6 +671,10 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
 
 #pragma unroll
     for (int k = 0; k < CY; ++k) dst[(int64_t)(j * CY + k) * st] = v[k];
+
+    // last sweep of the step: block 0 closes the step (the pass-A partials are
+    // complete, since pass A ran to the end before this launch)
+    if (a.fin.enabled && blockIdx.x == 0) finalize(a.fin, tid, blockDim.x);
 }
 
 // --------------------------------------------------------------------------
@@ -686,15 +699,14 @@ __global__ void init_kernel(T* C, int64_t sites, uint64_t seed, double c0, doubl
     }
 }
 
-__global__ void reset_kernel(int64_t* steps, int nsteps, int64_t value, uint32_t* done, int ndone,
-                             int32_t* flags, int m, double* series, int64_t series_len)
+__global__ void reset_kernel(int64_t* steps, int nsteps, int64_t value, int32_t* flags, int m,
+                             double* series, int64_t series_len)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t T = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = t; i < series_len; i += T) series[i] = __builtin_nan("");
-    for (int64_t i = t; i < nsteps; i += T) steps[i] = value;
-    for (int64_t i = t; i < ndone; i += T) done[i] = 0u;
-    for (int64_t i = t; i < m; i += T) flags[i] = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = t; i < series_len; i += stride) series[i] = __builtin_nan("");
+    for (int64_t i = t; i < nsteps; i += stride) steps[i] = value;
+    for (int64_t i = t; i < m; i += stride) flags[i] = 0;
 }
 
 // Sample j (n = jK): t, F, G_fd, G_id, beta, <C>.  G_fd is the central
@@ -789,7 +801,10 @@ static hipError_t launchC_cy(int cy, const ColArgs& a, hipStream_t s)
     case 8: return launchC<T, 8>(a, s);
     case 16: return launchC<T, 16>(a, s);
     case 32: return launchC<T, 32>(a, s);
-    case 64: return launchC<T, 64>(a, s);
+    case 64:
+        // 64 doubles per lane exceed the register file: FP32 only
+        if constexpr (sizeof(T) == 4) return launchC<T, 64>(a, s);
+        return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
@@ -820,13 +835,19 @@ hipError_t launch_init_member(int prec, void* C, int64_t sites, uint64_t seed, d
     return hipGetLastError();
 }
 
-hipError_t launch_reset(int64_t* steps, int nsteps, int64_t value, uint32_t* done, int ndone,
-                        int32_t* flags, int m, double* series, int64_t series_len, hipStream_t s)
+hipError_t launch_reset(int64_t* steps, int nsteps, int64_t value, int32_t* flags, int m,
+                        double* series, int64_t series_len, hipStream_t s)
 {
-    int64_t big = std::max<int64_t>(series_len, std::max<int64_t>(m, std::max(nsteps, ndone)));
+    const int64_t big = std::max<int64_t>(series_len, std::max<int64_t>(m, nsteps));
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((big + 255) / 256, 4096));
     hipLaunchKernelGGL(reset_kernel, dim3((unsigned)blocks), dim3(256), 0, s, steps, nsteps, value,
-                       done, ndone, flags, m, series, series_len);
+                       flags, m, series, series_len);
+    return hipGetLastError();
+}
+
+hipError_t launch_fin(const FinArgs& f, hipStream_t s)
+{
+    hipLaunchKernelGGL(fin_kernel, dim3(1), dim3(256), 0, s, f);
     return hipGetLastError();
 }
 
