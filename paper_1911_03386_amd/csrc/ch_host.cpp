@@ -46,7 +46,7 @@ struct ClassPlan {
     int dim = 2, nx = 0, ny = 0, nz = 1;
     std::vector<int> members;
     // pass A
-    int cx = 0, waves = 4, P = 0, rpw = 0, R = 0, bands = 0, pitch = 0;
+    int cx = 0, rl = 1, waves = 4, P = 0, rpw = 0, R = 0, bands = 0, pitch = 0;
     int64_t nblocksA = 0;
     size_t ldsA = 0;
     ColPlan col[3];  // [1] = y, [2] = z
@@ -66,13 +66,13 @@ int elem_size(int prec) { return prec == 0 ? 8 : 4; }
 
 int lds_pos(int xx, int cx, int pad) { return xx + (xx / cx) * pad; }
 
-bool planA(ClassPlan& c, int prec, int cx, int waves)
+bool planA(ClassPlan& c, int prec, int cx, int rl, int waves)
 {
-    if (!passA_has(c.dim, cx) || c.nx % cx) return false;
+    if (!passA_has(c.dim, cx, rl) || c.nx % cx) return false;
     const int P = c.nx / cx;
     if (P < 1 || P > 64) return false;
     if (waves < 1 || waves > kPassAThreads / 64) return false;
-    const int rpw = 64 / P;
+    const int rpw = (64 / P) * rl;
     const int R = waves * rpw;
     const int pad = passA_pad(prec);
     const int pitch = lds_pos(c.nx + 2 * kHalo - 1, cx, pad) + 1;
@@ -80,6 +80,7 @@ bool planA(ClassPlan& c, int prec, int cx, int waves)
     const size_t lds = (size_t)planes * (R + 3) * pitch * elem_size(prec);
     if (lds > kLdsLimit) return false;
     c.cx = cx;
+    c.rl = rl;
     c.waves = waves;
     c.P = P;
     c.rpw = rpw;
@@ -116,10 +117,11 @@ bool planCol(ClassPlan& c, int prec, int axis, int cy, int b)
 
 bool default_A(ClassPlan& c, int prec)
 {
-    const int prefs[] = {16, 8, 32, 4, 64};
+    const int prefs[][2] = {{16, 2}, {16, 1}, {8, 2}, {8, 1}, {32, 1}, {4, 2}, {4, 1}, {32, 2},
+                            {64, 1}, {4, 4}, {8, 4}, {16, 4}};
     for (int waves : {4, 2, 1})
-        for (int cx : prefs)
-            if (planA(c, prec, cx, waves)) return true;
+        for (auto& p : prefs)
+            if (planA(c, prec, p[0], p[1], waves)) return true;
     return false;
 }
 
@@ -241,6 +243,17 @@ void axis_coef(double rho, int n, int chunk, int prec, AxisCoef& out)
     out.a1 = (double)a1;
     out.a2 = (double)a2;
     out.ikappa = (double)(q1 * q1);
+    out.inv_n = (double)(1.0L / n);
+    {
+        LD s0 = 0, s1 = 0;  // zero-state recursion over a chunk of ones
+        for (int k = 0; k < chunk; ++k) {
+            const LD u = 1.0L + a1 * s0 + a2 * s1;
+            s1 = s0;
+            s0 = u;
+        }
+        out.E1[0] = (double)s0;
+        out.E1[1] = (double)s1;
+    }
     auto mul = [](const LD* A, const LD* B, LD* C) {
         LD c0 = A[0] * B[0] + A[1] * B[2], c1 = A[0] * B[1] + A[1] * B[3];
         LD c2 = A[2] * B[0] + A[3] * B[2], c3 = A[2] * B[1] + A[3] * B[3];
@@ -510,7 +523,7 @@ hipError_t launch_A(ch_ctx* ctx, int ci, int mode)
 {
     ClassPlan& c = ctx->classes[ci];
     PassAArgs a = passA_args(ctx, ci, mode);
-    return launch_passA(ctx->prec, c.dim, c.cx, a, c.ldsA, ctx->stream);
+    return launch_passA(ctx->prec, c.dim, c.cx, c.rl, a, c.ldsA, ctx->stream);
 }
 
 // the column sweeps of one step: 2D  w -> C ;  3D  w -> w (y), w -> C (z)
@@ -601,8 +614,9 @@ std::string plan_text(const ch_ctx* ctx)
     std::string s;
     char buf[320];
     for (const auto& c : ctx->classes) {
-        snprintf(buf, sizeof buf, "%dD %dx%dx%d %s x%zu: A cx=%d P=%d waves=%d R=%d blocks=%lld lds=%zu",
-                 c.dim, c.nx, c.ny, c.nz, ctx->prec ? "f32" : "f64", c.members.size(), c.cx, c.P,
+        snprintf(buf, sizeof buf,
+                 "%dD %dx%dx%d %s x%zu: A cx=%d rl=%d P=%d waves=%d R=%d blocks=%lld lds=%zu", c.dim,
+                 c.nx, c.ny, c.nz, ctx->prec ? "f32" : "f64", c.members.size(), c.cx, c.rl, c.P,
                  c.waves, c.R, (long long)c.nblocksA, c.ldsA);
         s += buf;
         for (int a = 1; a < c.dim; ++a) {
@@ -958,14 +972,15 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
 {
     ch_status st = check_ctx(ctx);
     if (st != CH_OK) return st;
-    // cached choices: one line per class "key cx waves cy_y b_y cy_z b_z"
+    // cached choices: one line per class "key cx rl waves cy_y b_y cy_z b_z"
     std::map<std::string, std::vector<int>> cache;
     if (cache_path) {
         if (FILE* f = fopen(cache_path, "r")) {
             char key[256];
-            int v[6];
-            while (fscanf(f, "%255s %d %d %d %d %d %d", key, &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) == 7)
-                cache[key] = std::vector<int>(v, v + 6);
+            int v[7];
+            while (fscanf(f, "%255s %d %d %d %d %d %d %d", key, &v[0], &v[1], &v[2], &v[3], &v[4], &v[5],
+                          &v[6]) == 8)
+                cache[key] = std::vector<int>(v, v + 7);
             fclose(f);
         }
     }
@@ -993,8 +1008,8 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
         if (hit != cache.end()) {
             const std::vector<int>& v = hit->second;
             ClassPlan t = c;
-            bool ok = planA(t, ctx->prec, v[0], v[1]) && planCol(t, ctx->prec, 1, v[2], v[3]) &&
-                      (c.dim == 2 || planCol(t, ctx->prec, 2, v[4], v[5]));
+            bool ok = planA(t, ctx->prec, v[0], v[1], v[2]) && planCol(t, ctx->prec, 1, v[3], v[4]) &&
+                      (c.dim == 2 || planCol(t, ctx->prec, 2, v[5], v[6]));
             if (ok) {
                 c = t;
                 continue;
@@ -1002,29 +1017,31 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
         }
         // pass A candidates (timing mode: reads C, writes the scratch field)
         float best = 1e30f;
-        int bcx = c.cx, bw = c.waves;
+        int bcx = c.cx, brl = c.rl, bw = c.waves;
         for (int waves : {4, 2, 1})
-            for (int cx : {4, 8, 16, 32, 64}) {
-                ClassPlan t = c;
-                if (!planA(t, ctx->prec, cx, waves)) continue;
-                ctx->classes[ci] = t;
-                fill_member_table(ctx);
-                if ((st = upload_tables(ctx)) != CH_OK) {
-                    ctx->classes[ci] = c;
-                    return st;
+            for (int rl : {1, 2, 4})
+                for (int cx : {4, 8, 16, 32, 64}) {
+                    ClassPlan t = c;
+                    if (!planA(t, ctx->prec, cx, rl, waves)) continue;
+                    ctx->classes[ci] = t;
+                    fill_member_table(ctx);
+                    if ((st = upload_tables(ctx)) != CH_OK) {
+                        ctx->classes[ci] = c;
+                        return st;
+                    }
+                    float ms = 0;
+                    err = time_it([&] { return launch_A(ctx, ci, MODE_TIMING); }, ms);
+                    if (err != hipSuccess) break;
+                    if (ms < best) {
+                        best = ms;
+                        bcx = cx;
+                        brl = rl;
+                        bw = waves;
+                    }
                 }
-                float ms = 0;
-                err = time_it([&] { return launch_A(ctx, ci, MODE_TIMING); }, ms);
-                if (err != hipSuccess) break;
-                if (ms < best) {
-                    best = ms;
-                    bcx = cx;
-                    bw = waves;
-                }
-            }
         ctx->classes[ci] = c;
         if (err != hipSuccess) break;
-        planA(c, ctx->prec, bcx, bw);
+        planA(c, ctx->prec, bcx, brl, bw);
         ctx->classes[ci] = c;
         // column sweeps, in place on the scratch field
         for (int axis = 1; axis < c.dim && err == hipSuccess; ++axis) {
@@ -1065,7 +1082,7 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
             planCol(c, ctx->prec, axis, bcy, bb);
             ctx->classes[ci] = c;
         }
-        cache[key] = {c.cx, c.waves, c.col[1].cy, c.col[1].b, c.dim == 3 ? c.col[2].cy : 0,
+        cache[key] = {c.cx, c.rl, c.waves, c.col[1].cy, c.col[1].b, c.dim == 3 ? c.col[2].cy : 0,
                       c.dim == 3 ? c.col[2].b : 0};
     }
     (void)hipEventDestroy(e0);
@@ -1078,8 +1095,8 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
     if (cache_path) {
         if (FILE* f = fopen(cache_path, "w")) {
             for (auto& kv : cache)
-                fprintf(f, "%s %d %d %d %d %d %d\n", kv.first.c_str(), kv.second[0], kv.second[1],
-                        kv.second[2], kv.second[3], kv.second[4], kv.second[5]);
+                fprintf(f, "%s %d %d %d %d %d %d %d\n", kv.first.c_str(), kv.second[0], kv.second[1],
+                        kv.second[2], kv.second[3], kv.second[4], kv.second[5], kv.second[6]);
             fclose(f);
         }
     }
@@ -1094,14 +1111,14 @@ ch_status ch_num_classes(const ch_ctx* ctx, int32_t* nclasses)
     return CH_OK;
 }
 
-ch_status ch_set_tiles(ch_ctx* ctx, int32_t cls, int32_t cx, int32_t waves, int32_t cy, int32_t by,
-                       int32_t cz, int32_t bz)
+ch_status ch_set_tiles(ch_ctx* ctx, int32_t cls, int32_t cx, int32_t rl, int32_t waves, int32_t cy,
+                       int32_t by, int32_t cz, int32_t bz)
 {
     ch_status st = check_ctx(ctx);
     if (st != CH_OK) return st;
     if (cls < 0 || cls >= (int)ctx->classes.size()) return fail(ctx, CH_EINVAL, "bad class index");
     ClassPlan t = ctx->classes[cls];
-    if (!planA(t, ctx->prec, cx, waves) || !planCol(t, ctx->prec, 1, cy, by) ||
+    if (!planA(t, ctx->prec, cx, rl, waves) || !planCol(t, ctx->prec, 1, cy, by) ||
         (t.dim == 3 && !planCol(t, ctx->prec, 2, cz, bz)))
         return fail(ctx, CH_EUNSUPPORTED, "tile shape not valid for class %d", cls);
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));

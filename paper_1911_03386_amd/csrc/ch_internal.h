@@ -23,6 +23,9 @@ constexpr int kHalo = 2;           // halo columns kept on each side of an LDS r
 // A = [[a1, a2], [1, 0]].
 struct AxisCoef {
     double a1, a2, ikappa;
+    double inv_n;                    // 1 / line length (the line mean is passed around
+                                     // the recursions, which then see zero-mean data)
+    double E1[2];                    // zero-state end state of a chunk of ones
     double M[4];                     // A^c, c = chunk length (row-major)
     double Mp[kMaxScanLevels][4];    // (A^c)^(2^s)
     double W[4];                     // (I - A^n)^{-1}, n = line length
@@ -69,7 +72,7 @@ struct PassAArgs {
     int32_t nmem;              // members in this class
     int32_t nx, ny, nz;
     int32_t P;                 // lanes per x-line (chunks)
-    int32_t rows_per_wave;     // x-lines per wavefront
+    int32_t rows_per_wave;     // x-lines per wavefront (line groups x lines per lane)
     int32_t waves;             // wavefronts per block (1, 2 or 4)
     int32_t R;                 // x-lines per block (= waves * rows_per_wave)
     int32_t bands_y;           // y-bands per (member, z) = ceil(ny / R)
@@ -101,7 +104,7 @@ struct ColArgs {
 
 // Kernel launchers (ch_kernels.hip).  prec: 0 = double, 1 = float.  They
 // return hipErrorInvalidValue for an uninstantiated chunk length.
-hipError_t launch_passA(int prec, int dim, int cx, const PassAArgs& a, size_t lds_bytes,
+hipError_t launch_passA(int prec, int dim, int cx, int rl, const PassAArgs& a, size_t lds_bytes,
                         hipStream_t s);
 hipError_t launch_col(int prec, int cy, const ColArgs& a, hipStream_t s);
 hipError_t launch_init_member(int prec, void* C, int64_t sites, uint64_t seed, double c0,
@@ -112,7 +115,7 @@ hipError_t launch_fin(const FinArgs& f, hipStream_t s);
 hipError_t launch_beta(const double* series, int64_t max_samples, int32_t member, int32_t K,
                        int64_t ncur, double dt, double* out, int64_t J, hipStream_t s);
 
-bool passA_has(int dim, int cx);
+bool passA_has(int dim, int cx, int rl);
 bool col_has(int prec, int cy);
 int passA_pad(int prec);       // LDS padding (elements) after every chunk
 

@@ -103,11 +103,11 @@ __device__ __forceinline__ void fwd_zero(const T (&v)[CL], T a1, T a2, T& e0, T&
 }
 
 template <typename T, int CL>
-__device__ __forceinline__ void fwd_true(T (&v)[CL], T a1, T a2, T s0, T s1)
+__device__ __forceinline__ void fwd_true(T (&v)[CL], T a1, T a2, T s0, T s1, T m)
 {
 #pragma unroll
     for (int k = 0; k < CL; ++k) {
-        T u = fma(a1, s0, fma(a2, s1, v[k]));
+        T u = fma(a1, s0, fma(a2, s1, v[k] - m));
         s1 = s0;
         s0 = u;
         v[k] = u;
@@ -130,89 +130,133 @@ __device__ __forceinline__ void bwd_zero(const T (&v)[CL], T a1, T a2, T& e0, T&
 }
 
 template <typename T, int CL>
-__device__ __forceinline__ void bwd_true(T (&v)[CL], T a1, T a2, T s0, T s1, T ik)
+__device__ __forceinline__ void bwd_true(T (&v)[CL], T a1, T a2, T s0, T s1, T ik, T m)
 {
 #pragma unroll
     for (int k = CL - 1; k >= 0; --k) {
         T u = fma(a1, s0, fma(a2, s1, v[k]));
         s1 = s0;
         s0 = u;
-        v[k] = u * ik;
+        v[k] = fma(u, ik, m);
     }
 }
 
-// Scan of chunk end states over the P lanes of one group inside a wavefront
-// (lanes gbase .. gbase+P-1, chunk j = lane - gbase).  On return (e0, e1) is
-// the true state entering chunk j.  All 64 lanes must call it (P is uniform).
-template <typename T>
-__device__ __forceinline__ void scan_fwd_wave(T& e0, T& e1, int j, int P, int gbase,
-                                              const LineCoef<T>& c)
+// Cross-lane moves with precomputed ds_bpermute byte addresses (lane * 4).
+__device__ __forceinline__ float lane_get(int addr, float v)
 {
-    T x0 = e0, x1 = e1;
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_get(int addr, double v)
+{
+    const int2 w = *reinterpret_cast<int2*>(&v);
+    int2 r;
+    r.x = __builtin_amdgcn_ds_bpermute(addr, w.x);
+    r.y = __builtin_amdgcn_ds_bpermute(addr, w.y);
+    return *reinterpret_cast<double*>(&r);
+}
+
+// Source addresses of the wavefront scans: up[s] = lane - 2^s, dn[s] = lane + 2^s
+// (wrapped; only read where the source lies in the same line), and the first
+// and last lane of the line.
+struct ScanLanes {
+    int up[kWaveScanLevels], dn[kWaveScanLevels];
+    int first, last;
+};
+
+__device__ __forceinline__ void make_lanes(ScanLanes& L, int lane, int gbase, int P)
+{
+#pragma unroll
+    for (int s = 0; s < kWaveScanLevels; ++s) {
+        L.up[s] = ((lane - (1 << s)) & 63) << 2;
+        L.dn[s] = ((lane + (1 << s)) & 63) << 2;
+    }
+    L.first = (gbase & 63) << 2;
+    L.last = ((gbase + P - 1) & 63) << 2;
+}
+
+// Scans of chunk end states over the P lanes of a line inside a wavefront
+// (chunk j = lane - first lane of the line), for RL independent lines held by
+// the same lanes.  On return (e0[q], e1[q]) is the true state entering chunk
+// j of line q.  All 64 lanes must call them (P is uniform).
+template <typename T, int RL>
+__device__ __forceinline__ void scan_fwd_wave(T (&e0)[RL], T (&e1)[RL], int j, int P,
+                                              const ScanLanes& L, const LineCoef<T>& c)
+{
 #pragma unroll
     for (int s = 0; s < kWaveScanLevels; ++s) {
         const int d = 1 << s;
         if (d < P) {
-            T y0 = __shfl_up(x0, d, 64);
-            T y1 = __shfl_up(x1, d, 64);
-            if (j >= d) {
-                mv(c.Mp[s], y0, y1);
-                x0 += y0;
-                x1 += y1;
+#pragma unroll
+            for (int q = 0; q < RL; ++q) {
+                T y0 = lane_get(L.up[s], e0[q]);
+                T y1 = lane_get(L.up[s], e1[q]);
+                if (j >= d) {
+                    mv(c.Mp[s], y0, y1);
+                    e0[q] += y0;
+                    e1[q] += y1;
+                }
             }
         }
     }
-    T z0 = __shfl(x0, gbase + P - 1, 64);
-    T z1 = __shfl(x1, gbase + P - 1, 64);
-    T r0 = c.W[0] * z0 + c.W[1] * z1;  // state after the whole line = entering chunk 0
-    T r1 = c.W[2] * z0 + c.W[3] * z1;
-    T p0 = __shfl_up(x0, 1, 64);
-    T p1 = __shfl_up(x1, 1, 64);
-    if (j == 0) {
-        p0 = T(0);
-        p1 = T(0);
-    }
 #pragma unroll
-    for (int s = 0; s < kWaveScanLevels; ++s)
-        if (((1 << s) < P) && (j & (1 << s))) mv(c.Mp[s], r0, r1);
-    e0 = p0 + r0;
-    e1 = p1 + r1;
+    for (int q = 0; q < RL; ++q) {
+        const T z0 = lane_get(L.last, e0[q]);
+        const T z1 = lane_get(L.last, e1[q]);
+        T r0 = c.W[0] * z0 + c.W[1] * z1;  // state after the whole line = entering chunk 0
+        T r1 = c.W[2] * z0 + c.W[3] * z1;
+        T p0 = lane_get(L.up[0], e0[q]);
+        T p1 = lane_get(L.up[0], e1[q]);
+        if (j == 0) {
+            p0 = T(0);
+            p1 = T(0);
+        }
+#pragma unroll
+        for (int s = 0; s < kWaveScanLevels; ++s)
+            if (((1 << s) < P) && (j & (1 << s))) mv(c.Mp[s], r0, r1);
+        e0[q] = p0 + r0;
+        e1[q] = p1 + r1;
+    }
 }
 
-template <typename T>
-__device__ __forceinline__ void scan_bwd_wave(T& e0, T& e1, int j, int P, int gbase,
-                                              const LineCoef<T>& c)
+template <typename T, int RL>
+__device__ __forceinline__ void scan_bwd_wave(T (&e0)[RL], T (&e1)[RL], int j, int P,
+                                              const ScanLanes& L, const LineCoef<T>& c)
 {
-    T x0 = e0, x1 = e1;
 #pragma unroll
     for (int s = 0; s < kWaveScanLevels; ++s) {
         const int d = 1 << s;
         if (d < P) {
-            T y0 = __shfl_down(x0, d, 64);
-            T y1 = __shfl_down(x1, d, 64);
-            if (j + d < P) {
-                mv(c.Mp[s], y0, y1);
-                x0 += y0;
-                x1 += y1;
+#pragma unroll
+            for (int q = 0; q < RL; ++q) {
+                T y0 = lane_get(L.dn[s], e0[q]);
+                T y1 = lane_get(L.dn[s], e1[q]);
+                if (j + d < P) {
+                    mv(c.Mp[s], y0, y1);
+                    e0[q] += y0;
+                    e1[q] += y1;
+                }
             }
         }
     }
-    T z0 = __shfl(x0, gbase, 64);
-    T z1 = __shfl(x1, gbase, 64);
-    T r0 = c.W[0] * z0 + c.W[1] * z1;  // state at the line start = entering chunk P-1
-    T r1 = c.W[2] * z0 + c.W[3] * z1;
-    T p0 = __shfl_down(x0, 1, 64);
-    T p1 = __shfl_down(x1, 1, 64);
-    if (j == P - 1) {
-        p0 = T(0);
-        p1 = T(0);
-    }
-    const int q = P - 1 - j;
+    const int qq = P - 1 - j;
 #pragma unroll
-    for (int s = 0; s < kWaveScanLevels; ++s)
-        if (((1 << s) < P) && (q & (1 << s))) mv(c.Mp[s], r0, r1);
-    e0 = p0 + r0;
-    e1 = p1 + r1;
+    for (int q = 0; q < RL; ++q) {
+        const T z0 = lane_get(L.first, e0[q]);
+        const T z1 = lane_get(L.first, e1[q]);
+        T r0 = c.W[0] * z0 + c.W[1] * z1;  // state at the line start = entering chunk P-1
+        T r1 = c.W[2] * z0 + c.W[3] * z1;
+        T p0 = lane_get(L.dn[0], e0[q]);
+        T p1 = lane_get(L.dn[0], e1[q]);
+        if (j == P - 1) {
+            p0 = T(0);
+            p1 = T(0);
+        }
+#pragma unroll
+        for (int s = 0; s < kWaveScanLevels; ++s)
+            if (((1 << s) < P) && (qq & (1 << s))) mv(c.Mp[s], r0, r1);
+        e0[q] = p0 + r0;
+        e1[q] = p1 + r1;
+    }
 }
 
 // Per-member reduction of the pass-A partials, in block order with Neumaier
@@ -328,7 +372,7 @@ struct PadOf<float> {
 // --------------------------------------------------------------------------
 // pass A: RHS + diagnostics + x-line solves
 // --------------------------------------------------------------------------
-template <typename T, int DIM, int CX>
+template <typename T, int DIM, int CX, int RL>
 __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -372,51 +416,63 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     const int nrows = Ract + (needG ? 3 : 2);
     const int npl = (DIM == 3) ? (needG ? 4 : 3) : 1;
     {
+        // interior: 16-byte vector loads, one row segment per thread
         const int nvec = nx / VEC;
-        const int nrr = npl * nrows;
-        auto stage = [&](int rr, int xv) {
-            const int pl = rr / nrows, r = rr - pl * nrows;
-            const int zz = (DIM == 3) ? wrapi(z - 1 + pl, nz) : 0;
-            const int yy = wrapi(y0 - 1 + r, ny);
-            const T* src = C + ((int64_t)zz * ny + yy) * nx + xv * VEC;
-            T vals[VEC];
-            vec_get<T>(*reinterpret_cast<const VT*>(src), vals);
-            T* drow = sC + pl * planeStride + r * pitch;
+        const int rpi = nvec >= nthreads ? 1 : nthreads / nvec;  // rows per sweep
+        const int r0 = nvec >= nthreads ? 0 : tid / nvec;
+        const int xv0 = nvec >= nthreads ? tid : tid - r0 * nvec;
+        const int xstep = nvec >= nthreads ? nthreads : nvec;
+        if (r0 < rpi) {
+            for (int pl = 0; pl < npl; ++pl) {
+                const int zz = (DIM == 3) ? wrapi(z - 1 + pl, nz) : 0;
+                T* dplane = sC + pl * planeStride;
+                for (int r = r0; r < nrows; r += rpi) {
+                    const int yy = wrapi(y0 - 1 + r, ny);
+                    const T* srow = C + ((int64_t)zz * ny + yy) * nx;
+                    T* drow = dplane + r * pitch;
+                    for (int xv = xv0; xv < nvec; xv += xstep) {
+                        T vals[VEC];
+                        vec_get<T>(*reinterpret_cast<const VT*>(srow + xv * VEC), vals);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                const int x = xv * VEC + e;
-                int xx = x + kHalo;
-                drow[xx + (xx / CX) * PADE] = vals[e];
-                if (x >= nx - kHalo) {
-                    xx = x - nx + kHalo;
-                    drow[xx + (xx / CX) * PADE] = vals[e];
-                }
-                if (x < kHalo) {
-                    xx = x + nx + kHalo;
-                    drow[xx + (xx / CX) * PADE] = vals[e];
+                        for (int e = 0; e < VEC; ++e) {
+                            const int xx = xv * VEC + e + kHalo;
+                            drow[xx + (xx / CX) * PADE] = vals[e];
+                        }
+                    }
                 }
             }
-        };
-        if (nvec >= nthreads) {
-            for (int rr = 0; rr < nrr; ++rr)
-                for (int xv = tid; xv < nvec; xv += nthreads) stage(rr, xv);
-        } else {
-            const int rpi = nthreads / nvec;
-            const int r0 = tid / nvec, xv = tid - r0 * nvec;
-            if (r0 < rpi)
-                for (int rr = r0; rr < nrr; rr += rpi) stage(rr, xv);
+        }
+        // periodic halo columns: 2 on each side of every staged row
+        const int nh = npl * nrows * 2 * kHalo;
+        for (int i = tid; i < nh; i += nthreads) {
+            const int h = i & (2 * kHalo - 1), rr = i >> 2;
+            const int pl = (DIM == 3) ? rr / nrows : 0, r = rr - pl * nrows;
+            const int zz = (DIM == 3) ? wrapi(z - 1 + pl, nz) : 0;
+            const int yy = wrapi(y0 - 1 + r, ny);
+            const int xs = h < kHalo ? nx - kHalo + h : h - kHalo;  // source column
+            const int xx = h < kHalo ? h : nx + h;                  // LDS column
+            sC[pl * planeStride + r * pitch + xx + (xx / CX) * PADE] =
+                C[((int64_t)zz * ny + yy) * nx + xs];
         }
     }
     __syncthreads();
 
-    // ---- per-lane work: one chunk of CX elements of one x-line --------------
+    // ---- per-lane work: one chunk of CX elements of RL adjacent x-lines ------
+    // Lanes j = 0..P-1 of a group hold consecutive chunks of the same RL lines;
+    // sharing rows between the RL lines of a lane saves stencil work, and the
+    // RL independent recursions interleave.
     const int P = a.P;
-    const int g = lane / P;
-    const int j = lane - g * P;
-    const int r = wave * a.rows_per_wave + g;  // x-line within the block
-    const bool active = (g < a.rows_per_wave) && (r < Ract);
+    const int g = lane / P;                   // line group within the wavefront
+    const int j = lane - g * P;               // chunk index along the line
+    const int groups = a.rows_per_wave / RL;  // line groups per wavefront
+    const int rl0 = (wave * groups + g) * RL; // first x-line of this lane in the block
+    const bool lane_ok = g < groups;
+    bool rowok[RL];
+#pragma unroll
+    for (int q = 0; q < RL; ++q) rowok[q] = lane_ok && (rl0 + q < Ract);
+    const bool active = rowok[0];
     constexpr int PL0 = (DIM == 3) ? 1 : 0;
-    const T* cb = sC + PL0 * planeStride + (r + 1) * pitch + j * (CX + PADE);
+    const T* cb = sC + PL0 * planeStride + (rl0 + 1) * pitch + j * (CX + PADE);
 #define AT(dz, dy, m) cb[(dz) * planeStride + (dy) * pitch + (m) + ((m) / CX) * PADE]
 
     const T ihx2 = (T)md.ih2[0], ihy2 = (T)md.ih2[1], ihz2 = (T)md.ih2[2];
@@ -424,9 +480,11 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     const T cxy = (T)(md.ih2[0] * md.ih2[1]);
     const T cxz = (T)(md.ih2[0] * md.ih2[2]), cyz = (T)(md.ih2[1] * md.ih2[2]);
 
-    T v[CX];
+    T v[RL][CX];
 #pragma unroll
-    for (int k = 0; k < CX; ++k) v[k] = T(0);
+    for (int q = 0; q < RL; ++q)
+#pragma unroll
+        for (int k = 0; k < CX; ++k) v[q][k] = T(0);
 
     double pF = 0.0, pS = 0.0, pG = 0.0;
     if (active) {
@@ -434,29 +492,35 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
 #pragma unroll
             for (int k = 0; k < CX; ++k) {
                 const int m0 = k + kHalo;
-                const T c = AT(0, 0, m0), cw = AT(0, 0, m0 - 1), ce = AT(0, 0, m0 + 1);
-                const T cn = AT(0, 1, m0), cs = AT(0, -1, m0);
-                const T Nc = c * c * c - c;
-                const T Nw = cw * cw * cw - cw, Ne = ce * ce * ce - ce;
-                const T Nn = cn * cn * cn - cn, Ns = cs * cs * cs - cs;
-                T lapN = (Ne - T(2) * Nc + Nw) * ihx2 + (Nn - T(2) * Nc + Ns) * ihy2;
-                const T dxx0 = ce - T(2) * c + cw;
-                const T dxxn = AT(0, 1, m0 + 1) - T(2) * cn + AT(0, 1, m0 - 1);
-                const T dxxs = AT(0, -1, m0 + 1) - T(2) * cs + AT(0, -1, m0 - 1);
-                T cross = (dxxn - T(2) * dxx0 + dxxs) * cxy;
-                if (DIM == 3) {
-                    const T cu = AT(1, 0, m0), cd = AT(-1, 0, m0);
-                    const T Nu = cu * cu * cu - cu, Nd = cd * cd * cd - cd;
-                    lapN += (Nu - T(2) * Nc + Nd) * ihz2;
-                    const T dxxu = AT(1, 0, m0 + 1) - T(2) * cu + AT(1, 0, m0 - 1);
-                    const T dxxd = AT(-1, 0, m0 + 1) - T(2) * cd + AT(-1, 0, m0 - 1);
-                    cross += (dxxu - T(2) * dxx0 + dxxd) * cxz;
-                    const T dyy0 = cn - T(2) * c + cs;
-                    const T dyyu = AT(1, 1, m0) - T(2) * cu + AT(1, -1, m0);
-                    const T dyyd = AT(-1, 1, m0) - T(2) * cd + AT(-1, -1, m0);
-                    cross += (dyyu - T(2) * dyy0 + dyyd) * cyz;
+                // N = C^3 - C and the x second difference of C on lines -1 .. RL
+                T Nr[RL + 2], Dx[RL + 2];
+#pragma unroll
+                for (int q = 0; q < RL + 2; ++q) {
+                    const T c = AT(0, q - 1, m0);
+                    Nr[q] = c * c * c - c;
+                    Dx[q] = AT(0, q - 1, m0 + 1) - T(2) * c + AT(0, q - 1, m0 - 1);
                 }
-                v[k] = c + dt * lapN - tg * cross;
+#pragma unroll
+                for (int q = 0; q < RL; ++q) {
+                    const T c = AT(0, q, m0), cw = AT(0, q, m0 - 1), ce = AT(0, q, m0 + 1);
+                    const T Nw = cw * cw * cw - cw, Ne = ce * ce * ce - ce;
+                    const T Nc = Nr[q + 1];
+                    T lapN = (Ne - T(2) * Nc + Nw) * ihx2 + (Nr[q + 2] - T(2) * Nc + Nr[q]) * ihy2;
+                    T cross = (Dx[q + 2] - T(2) * Dx[q + 1] + Dx[q]) * cxy;
+                    if (DIM == 3) {
+                        const T cu = AT(1, q, m0), cd = AT(-1, q, m0);
+                        const T Nu = cu * cu * cu - cu, Nd = cd * cd * cd - cd;
+                        lapN += (Nu - T(2) * Nc + Nd) * ihz2;
+                        const T dxxu = AT(1, q, m0 + 1) - T(2) * cu + AT(1, q, m0 - 1);
+                        const T dxxd = AT(-1, q, m0 + 1) - T(2) * cd + AT(-1, q, m0 - 1);
+                        cross += (dxxu - T(2) * Dx[q + 1] + dxxd) * cxz;
+                        const T dyy0 = AT(0, q + 1, m0) - T(2) * c + AT(0, q - 1, m0);
+                        const T dyyu = AT(1, q + 1, m0) - T(2) * cu + AT(1, q - 1, m0);
+                        const T dyyd = AT(-1, q + 1, m0) - T(2) * cd + AT(-1, q - 1, m0);
+                        cross += (dyyu - T(2) * dyy0 + dyyd) * cyz;
+                    }
+                    v[q][k] = c + dt * lapN - tg * cross;
+                }
             }
         }
         if (needF) {
@@ -464,19 +528,23 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
             const double hg = 0.5 * md.gamma;
             const double dx2 = md.ih2[0], dy2 = md.ih2[1], dz2 = md.ih2[2];
 #pragma unroll
-            for (int k = 0; k < CX; ++k) {
-                const int m0 = k + kHalo;
-                const double c = (double)AT(0, 0, m0);
-                const double ex = (double)AT(0, 0, m0 + 1) - c;
-                const double ey = (double)AT(0, 1, m0) - c;
-                double gr = ex * ex * dx2 + ey * ey * dy2;
-                if (DIM == 3) {
-                    const double ez = (double)AT(1, 0, m0) - c;
-                    gr += ez * ez * dz2;
+            for (int q = 0; q < RL; ++q) {
+                if (!rowok[q]) continue;
+#pragma unroll
+                for (int k = 0; k < CX; ++k) {
+                    const int m0 = k + kHalo;
+                    const double c = (double)AT(0, q, m0);
+                    const double ex = (double)AT(0, q, m0 + 1) - c;
+                    const double ey = (double)AT(0, q + 1, m0) - c;
+                    double gr = ex * ex * dx2 + ey * ey * dy2;
+                    if (DIM == 3) {
+                        const double ez = (double)AT(1, q, m0) - c;
+                        gr += ez * ez * dz2;
+                    }
+                    const double qq = c * c - 1.0;
+                    pF += cbulk * qq * qq + hg * gr;
+                    pS += c;
                 }
-                const double q = c * c - 1.0;
-                pF += cbulk * q * q + hg * gr;
-                pS += c;
             }
         }
         if (needG) {
@@ -492,34 +560,70 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
                 return u * u * u - u - gam * l;
             };
 #pragma unroll
-            for (int k = 0; k < CX; ++k) {
-                const int m0 = k + kHalo;
-                const double mu = MU(0, 0, m0);
-                const double gx = MU(0, 0, m0 + 1) - mu;
-                const double gy = MU(0, 1, m0) - mu;
-                double q = gx * gx * dx2 + gy * gy * dy2;
-                if (DIM == 3) {
-                    const double gz = MU(1, 0, m0) - mu;
-                    q += gz * gz * dz2;
+            for (int q = 0; q < RL; ++q) {
+                if (!rowok[q]) continue;
+#pragma unroll
+                for (int k = 0; k < CX; ++k) {
+                    const int m0 = k + kHalo;
+                    const double mu = MU(0, q, m0);
+                    const double gx = MU(0, q, m0 + 1) - mu;
+                    const double gy = MU(0, q + 1, m0) - mu;
+                    double qq = gx * gx * dx2 + gy * gy * dy2;
+                    if (DIM == 3) {
+                        const double gz = MU(1, q, m0) - mu;
+                        qq += gz * gz * dz2;
+                    }
+                    pG += qq;
                 }
-                pG += q;
             }
         }
     }
 #undef AT
 
-    // ---- x-line solve (lanes of one line are contiguous in the wavefront) ---
+    // ---- x-line solves (lanes of one line are contiguous in the wavefront) ---
+    T mean[RL];
     if (solve) {
         LineCoef<T> cf;
         load_coef(cf, md.ax[0], P);
-        const int gbase = g * P;
-        T e0, e1;
-        fwd_zero(v, cf.a1, cf.a2, e0, e1);
-        scan_fwd_wave(e0, e1, j, P, gbase, cf);
-        fwd_true(v, cf.a1, cf.a2, e0, e1);
-        bwd_zero(v, cf.a1, cf.a2, e0, e1);
-        scan_bwd_wave(e0, e1, j, P, gbase, cf);
-        bwd_true(v, cf.a1, cf.a2, e0, e1, cf.ik);
+        ScanLanes SL;
+        make_lanes(SL, lane, g * P, P);
+        // the line mean passes through (I + rho D^4)^{-1} unchanged: take it out
+        // before the recursions and add it back at the end
+        T csum[RL];
+#pragma unroll
+        for (int q = 0; q < RL; ++q) {
+            csum[q] = T(0);
+#pragma unroll
+            for (int k = 0; k < CX; ++k) csum[q] += v[q][k];
+        }
+#pragma unroll
+        for (int s = 0; s < kWaveScanLevels; ++s) {
+            const int d = 1 << s;
+            if (d < P) {
+#pragma unroll
+                for (int q = 0; q < RL; ++q) {
+                    const T y = lane_get(SL.up[s], csum[q]);
+                    if (j >= d) csum[q] += y;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < RL; ++q) {
+            mean[q] = lane_get(SL.last, csum[q]) * (T)md.ax[0].inv_n;
+#pragma unroll
+            for (int k = 0; k < CX; ++k) v[q][k] -= mean[q];
+        }
+        T e0[RL], e1[RL];
+#pragma unroll
+        for (int q = 0; q < RL; ++q) fwd_zero(v[q], cf.a1, cf.a2, e0[q], e1[q]);
+        scan_fwd_wave<T, RL>(e0, e1, j, P, SL, cf);
+#pragma unroll
+        for (int q = 0; q < RL; ++q) fwd_true(v[q], cf.a1, cf.a2, e0[q], e1[q], T(0));
+#pragma unroll
+        for (int q = 0; q < RL; ++q) bwd_zero(v[q], cf.a1, cf.a2, e0[q], e1[q]);
+        scan_bwd_wave<T, RL>(e0, e1, j, P, SL, cf);
+#pragma unroll
+        for (int q = 0; q < RL; ++q) bwd_true(v[q], cf.a1, cf.a2, e0[q], e1[q], cf.ik, mean[q]);
     }
 
     // ---- diagnostics partials -------------------------------------------------
@@ -539,28 +643,36 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
 
     // ---- write w through LDS (coalesced) -------------------------------------
     if (solve) {
-        T* so = sC + (r + 1) * pitch + j * (CX + PADE);  // plane slot 0 is free now
-        if (active) {
+#pragma unroll
+        for (int q = 0; q < RL; ++q) {
+            if (!rowok[q]) continue;
+            T* so = sC + (rl0 + q + 1) * pitch + j * (CX + PADE);  // plane slot 0 is free now
 #pragma unroll
             for (int k = 0; k < CX; ++k) {
                 const int m = k + kHalo;
-                so[m + (m / CX) * PADE] = v[k];
+                so[m + (m / CX) * PADE] = v[q][k];
             }
         }
         __syncthreads();
         const int nvec = nx / VEC;
-        const int tot = Ract * nvec;
-        for (int i = tid; i < tot; i += nthreads) {
-            const int rr = i / nvec, xv = i - rr * nvec;
-            const T* srow = sC + (rr + 1) * pitch;
-            T vals[VEC];
+        const int rpi = nvec >= nthreads ? 1 : nthreads / nvec;
+        const int r0 = nvec >= nthreads ? 0 : tid / nvec;
+        const int xv0 = nvec >= nthreads ? tid : tid - r0 * nvec;
+        const int xstep = nvec >= nthreads ? nthreads : nvec;
+        if (r0 < rpi) {
+            for (int rr = r0; rr < Ract; rr += rpi) {
+                const T* srow = sC + (rr + 1) * pitch;
+                T* grow = Wout + ((int64_t)z * ny + y0 + rr) * nx;
+                for (int xv = xv0; xv < nvec; xv += xstep) {
+                    T vals[VEC];
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                const int xx = xv * VEC + e + kHalo;
-                vals[e] = srow[xx + (xx / CX) * PADE];
+                    for (int e = 0; e < VEC; ++e) {
+                        const int xx = xv * VEC + e + kHalo;
+                        vals[e] = srow[xx + (xx / CX) * PADE];
+                    }
+                    *reinterpret_cast<VT*>(grow + xv * VEC) = vec_make<T>(vals);
+                }
             }
-            *reinterpret_cast<VT*>(Wout + ((int64_t)z * ny + y0 + rr) * nx + xv * VEC) =
-                vec_make<T>(vals);
         }
     }
 
@@ -590,6 +702,8 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
     T* sE1 = sE0 + bP;
     T* sF0 = sE1 + bP;
     T* sF1 = sF0 + bP;
+    T* sS = sF1 + bP;  // chunk sums
+    T* sM = sS + bP;   // line means
 
     const int tid = threadIdx.x;
     const int j = tid / a.b;
@@ -618,22 +732,32 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
         W[i] = (T)ac.W[i];
     }
 
-    // causal recursion
-    T e0, e1;
+    // causal recursion.  The line mean m passes through the solve unchanged;
+    // the recursions run on v - m (chunk end states corrected by m * E1, the
+    // end state of a chunk of ones) and m is added back at the end.
+    const T E10 = (T)ac.E1[0], E11 = (T)ac.E1[1];
+    T e0, e1, csum = T(0);
+#pragma unroll
+    for (int k = 0; k < CY; ++k) csum += v[k];
     fwd_zero(v, a1, a2, e0, e1);
     sE0[j * a.b + c] = e0;
     sE1[j * a.b + c] = e1;
+    sS[j * a.b + c] = csum;
     __syncthreads();
     if (j == 0) {
+        T tot = T(0);
+        for (int q = 0; q < P; ++q) tot += sS[q * a.b + c];
+        const T mm = tot * (T)ac.inv_n;
+        sM[c] = mm;
         T z0 = T(0), z1 = T(0);
         for (int q = 0; q < P; ++q) {
             mv(M, z0, z1);
-            z0 += sE0[q * a.b + c];
-            z1 += sE1[q * a.b + c];
+            z0 += sE0[q * a.b + c] - mm * E10;
+            z1 += sE1[q * a.b + c] - mm * E11;
         }
         T s0 = W[0] * z0 + W[1] * z1, s1 = W[2] * z0 + W[3] * z1;
         for (int q = 0; q < P; ++q) {
-            const T f0 = sE0[q * a.b + c], f1 = sE1[q * a.b + c];
+            const T f0 = sE0[q * a.b + c] - mm * E10, f1 = sE1[q * a.b + c] - mm * E11;
             sE0[q * a.b + c] = s0;
             sE1[q * a.b + c] = s1;
             mv(M, s0, s1);
@@ -642,7 +766,8 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
         }
     }
     __syncthreads();
-    fwd_true(v, a1, a2, sE0[j * a.b + c], sE1[j * a.b + c]);
+    const T m = sM[c];
+    fwd_true(v, a1, a2, sE0[j * a.b + c], sE1[j * a.b + c], m);
 
     // anti-causal recursion
     bwd_zero(v, a1, a2, e0, e1);
@@ -667,7 +792,7 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
         }
     }
     __syncthreads();
-    bwd_true(v, a1, a2, sF0[j * a.b + c], sF1[j * a.b + c], ik);
+    bwd_true(v, a1, a2, sF0[j * a.b + c], sF1[j * a.b + c], ik, m);
 
 #pragma unroll
     for (int k = 0; k < CY; ++k) dst[(int64_t)(j * CY + k) * st] = v[k];
@@ -745,10 +870,10 @@ __global__ void beta_kernel(const double* series, int64_t max_samples, int32_t m
 // --------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------
-template <typename T, int DIM, int CX>
+template <typename T, int DIM, int CX, int RL>
 static hipError_t launchA(const PassAArgs& a, size_t lds, hipStream_t s)
 {
-    auto k = passA_kernel<T, DIM, CX>;
+    auto k = passA_kernel<T, DIM, CX, RL>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -758,37 +883,47 @@ static hipError_t launchA(const PassAArgs& a, size_t lds, hipStream_t s)
     return hipGetLastError();
 }
 
+// (chunk length, lines per lane) pairs that are compiled
+#define CH_PASSA_SHAPES(X) \
+    X(4, 1) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(4, 2) X(8, 2) X(16, 2) X(32, 2) X(4, 4) X(8, 4) X(16, 4)
+
 template <typename T, int DIM>
-static hipError_t launchA_cx(int cx, const PassAArgs& a, size_t lds, hipStream_t s)
+static hipError_t launchA_shape(int cx, int rl, const PassAArgs& a, size_t lds, hipStream_t s)
 {
-    switch (cx) {
-    case 4: return launchA<T, DIM, 4>(a, lds, s);
-    case 8: return launchA<T, DIM, 8>(a, lds, s);
-    case 16: return launchA<T, DIM, 16>(a, lds, s);
-    case 32: return launchA<T, DIM, 32>(a, lds, s);
-    case 64: return launchA<T, DIM, 64>(a, lds, s);
-    default: return hipErrorInvalidValue;
-    }
+#define X(C, R) \
+    if (cx == C && rl == R) return launchA<T, DIM, C, R>(a, lds, s);
+    CH_PASSA_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
 }
 
-bool passA_has(int dim, int cx)
+bool passA_has(int dim, int cx, int rl)
 {
-    return (dim == 2 || dim == 3) && (cx == 4 || cx == 8 || cx == 16 || cx == 32 || cx == 64);
+    if (dim != 2 && dim != 3) return false;
+#define X(C, R) \
+    if (cx == C && rl == R) return true;
+    CH_PASSA_SHAPES(X)
+#undef X
+    return false;
 }
 
 int passA_pad(int prec) { return prec == 0 ? PadOf<double>::v : PadOf<float>::v; }
 
-hipError_t launch_passA(int prec, int dim, int cx, const PassAArgs& a, size_t lds, hipStream_t s)
+hipError_t launch_passA(int prec, int dim, int cx, int rl, const PassAArgs& a, size_t lds,
+                        hipStream_t s)
 {
     if (a.nblocks <= 0) return hipSuccess;
-    if (prec == 0) return dim == 2 ? launchA_cx<double, 2>(cx, a, lds, s) : launchA_cx<double, 3>(cx, a, lds, s);
-    return dim == 2 ? launchA_cx<float, 2>(cx, a, lds, s) : launchA_cx<float, 3>(cx, a, lds, s);
+    if (prec == 0)
+        return dim == 2 ? launchA_shape<double, 2>(cx, rl, a, lds, s)
+                        : launchA_shape<double, 3>(cx, rl, a, lds, s);
+    return dim == 2 ? launchA_shape<float, 2>(cx, rl, a, lds, s)
+                    : launchA_shape<float, 3>(cx, rl, a, lds, s);
 }
 
 template <typename T, int CY>
 static hipError_t launchC(const ColArgs& a, hipStream_t s)
 {
-    const size_t lds = (size_t)4 * a.b * a.P * sizeof(T);
+    const size_t lds = ((size_t)5 * a.b * a.P + a.b) * sizeof(T);
     hipLaunchKernelGGL((col_kernel<T, CY>), dim3((unsigned)a.nblocks), dim3(a.b * a.P), lds, s, a);
     return hipGetLastError();
 }

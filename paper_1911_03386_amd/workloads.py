@@ -12,7 +12,7 @@ from typing import List
 
 import numpy as np
 
-from .ch import CH_F32_BULK, CH_F64, make_desc
+from .ch import CH_F32_BULK, CH_F64, make_desc  # noqa: F401  (make_desc re-exported)
 
 TWO_PI = 2 * np.pi
 

@@ -121,7 +121,8 @@ def _all_tiles(ens, cls, n, prec):
     out = []
     nx, ny = n
     for waves in (1, 2, 4):
-        for cx in (4, 8, 16, 32, 64):
+        for cx, rl in ((4, 1), (8, 1), (16, 1), (32, 1), (64, 1), (4, 2), (8, 2), (16, 2), (32, 2),
+                       (4, 4), (8, 4), (16, 4)):
             if nx % cx or nx // cx > 64:
                 continue
             for cy in (4, 8, 16, 32) + ((64,) if prec == CH_F32_BULK else ()):
@@ -130,7 +131,7 @@ def _all_tiles(ens, cls, n, prec):
                 P = ny // cy
                 for b in (1, 2, 4, 8, 16, 32, 64):
                     if nx % b == 0 and b * P <= 512:
-                        out.append((cx, waves, cy, b))
+                        out.append((cx, rl, waves, cy, b))
     return out
 
 
@@ -141,17 +142,17 @@ def test_every_tile_shape_parity_2d():
     Cref = oracle.step(_ref_field(d, (64, 128)), gamma, dt, N)
     ens = Ensemble([d], prec=CH_F64, cadence=5, max_samples=N // 5 + 1)
     tried = 0
-    for cx, waves, cy, b in _all_tiles(ens, 0, n, CH_F64):
+    for cx, rl, waves, cy, b in _all_tiles(ens, 0, n, CH_F64):
         try:
-            ens.set_tiles(0, cx, waves, cy, b)
+            ens.set_tiles(0, cx, rl, waves, cy, b)
         except ChError:
             continue
         ens.init_random()
         ens.step(N)
         err = float(np.abs(ens.get_field(0) - Cref).max())
-        assert err <= TOL, ((cx, waves, cy, b), err)
+        assert err <= TOL, ((cx, rl, waves, cy, b), err)
         tried += 1
-    assert tried >= 20
+    assert tried >= 40
     ens.close()
 
 
@@ -162,22 +163,22 @@ def test_every_tile_shape_parity_3d():
     Cref = oracle.step(_ref_field(d, (24, 16, 32)), gamma, dt, N)
     ens = Ensemble([d], prec=CH_F64, cadence=5, max_samples=N // 5 + 1)
     tried = 0
-    for cx in (4, 8, 16, 32):
+    for cx, rl in ((4, 1), (8, 1), (16, 1), (32, 1), (4, 2), (8, 2), (16, 2), (4, 4), (8, 4)):
         for waves in (1, 4):
             for cy, by in ((4, 8), (8, 32), (16, 2)):
                 for cz, bz in ((4, 32), (8, 16), (24 // 4, 1)):
                     if 24 % cz:
                         continue
                     try:
-                        ens.set_tiles(0, cx, waves, cy, by, cz, bz)
+                        ens.set_tiles(0, cx, rl, waves, cy, by, cz, bz)
                     except ChError:
                         continue
                     ens.init_random()
                     ens.step(N)
                     err = float(np.abs(ens.get_field(0) - Cref).max())
-                    assert err <= TOL, ((cx, waves, cy, by, cz, bz), err)
+                    assert err <= TOL, ((cx, rl, waves, cy, by, cz, bz), err)
                     tried += 1
-    assert tried >= 8
+    assert tried >= 16
 
 
 def test_graph_and_eager_bitwise_equal_and_deterministic():
