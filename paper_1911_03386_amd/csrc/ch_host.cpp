@@ -56,7 +56,7 @@ struct ClassPlan {
 };
 
 struct Layout {
-    size_t off_mem = 0, off_C = 0, off_W = 0, off_steps = 0, off_flags = 0;
+    size_t off_mem = 0, off_C = 0, off_W = 0, off_steps = 0, off_nstamp = 0, off_flags = 0;
     size_t off_series = 0, off_energy = 0, off_beta = 0, total = 0;
     int64_t total_elems = 0;
     std::vector<int64_t> moff;  // element offset per member
@@ -74,8 +74,9 @@ bool planA(ClassPlan& c, int prec, int cx, int rl, int waves)
     if (waves < 1 || waves > kPassAThreads / 64) return false;
     const int rpw = (64 / P) * rl;
     const int R = waves * rpw;
-    const int pad = passA_pad(prec);
-    const int pitch = lds_pos(c.nx + 2 * kHalo - 1, cx, pad) + 1;
+    const int pad = passA_pad(prec), halo = passA_halo(prec);
+    if (cx % halo) return false;
+    const int pitch = lds_pos(c.nx + 2 * halo - 1, cx, pad) + 1;
     const int planes = c.dim == 3 ? 4 : 1;
     const size_t lds = (size_t)planes * (R + 3) * pitch * elem_size(prec);
     if (lds > kLdsLimit) return false;
@@ -98,7 +99,10 @@ bool planCol(ClassPlan& c, int prec, int axis, int cy, int b)
     const int n = axis == 1 ? c.ny : c.nz;
     if (!col_has(prec, cy) || n % cy) return false;
     const int P = n / cy;
-    if (b < 1 || c.nx % b || b * P > kColMaxThreads || b * P < 1) return false;
+    // a block's b columns must be contiguous in memory: y-lines (and 2D) run
+    // along x only, z-lines along the whole x-y plane
+    const int64_t run = axis == 1 ? c.nx : (int64_t)c.nx * c.ny;
+    if (b < 1 || run % b || b * P > kColMaxThreads) return false;
     p.cy = cy;
     p.b = b;
     p.P = P;
@@ -125,11 +129,11 @@ bool default_A(ClassPlan& c, int prec)
     return false;
 }
 
-int best_b(int nx, int P)
+int best_b(int64_t run, int P)
 {
     int b = 1;
     for (int t = 2; t <= 64; t *= 2)
-        if (nx % t == 0 && t * P <= kColMaxThreads) b = t;
+        if (run % t == 0 && t * P <= kColMaxThreads) b = t;
     return b;
 }
 
@@ -141,7 +145,7 @@ bool default_col(ClassPlan& c, int prec, int axis)
     for (int cy : prefs) {
         if (!col_has(prec, cy) || n % cy) continue;
         const int P = n / cy;
-        const int b = best_b(c.nx, P);
+        const int b = best_b(axis == 1 ? (int64_t)c.nx : (int64_t)c.nx * c.ny, P);
         if (b * P > kColMaxThreads) continue;
         const int score = std::min(b * elem_size(prec), 256);
         if (score > bestscore) {
@@ -343,6 +347,8 @@ void layout(const ch_member_desc* members, int32_t m, int prec, int64_t max_samp
     }
     L.off_steps = o;
     o = align_up(o + sizeof(int64_t) * classes.size());
+    L.off_nstamp = o;
+    o = align_up(o + sizeof(int64_t) * classes.size());
     L.off_flags = o;
     o = align_up(o + sizeof(int32_t) * m);
     L.off_series = o;
@@ -379,6 +385,7 @@ struct ch_ctx {
     void* d_C() { return ws + L.off_C; }
     void* d_W() { return ws + L.off_W; }
     int64_t* d_steps() { return reinterpret_cast<int64_t*>(ws + L.off_steps); }
+    int64_t* d_nstamp() { return reinterpret_cast<int64_t*>(ws + L.off_nstamp); }
     int32_t* d_flags() { return reinterpret_cast<int32_t*>(ws + L.off_flags); }
     double* d_series() { return reinterpret_cast<double*>(ws + L.off_series); }
     double* d_energy() { return reinterpret_cast<double*>(ws + L.off_energy); }
@@ -474,6 +481,7 @@ PassAArgs passA_args(ch_ctx* ctx, int ci, int mode)
     a.K = ctx->K;
     a.step = ctx->d_steps() + ci;
     a.partials = reinterpret_cast<double*>(ctx->ws + c.off_partials);
+    a.nstamp = ctx->d_nstamp() + ci;
     return a;
 }
 
@@ -489,6 +497,8 @@ FinArgs fin_args(ch_ctx* ctx, int ci, int mode)
     f.K = ctx->K;
     f.blocks_per_member = (int64_t)c.nz * c.bands;
     f.partials = reinterpret_cast<const double*>(ctx->ws + c.off_partials);
+    f.nstamp = ctx->d_nstamp() + ci;
+    f.G = (int32_t)std::min<int64_t>(c.members.size(), 1024);
     f.max_samples = ctx->max_samples;
     f.step = ctx->d_steps() + ci;
     f.series = ctx->d_series();
@@ -515,7 +525,10 @@ ColArgs col_args(ch_ctx* ctx, int ci, int axis, const void* src, void* dst, bool
     a.b = p.b;
     a.P = p.P;
     a.nblocks = p.nblocks;
-    if (closes_step) a.fin = fin_args(ctx, ci, MODE_STEP);
+    if (closes_step) {
+        a.fin = fin_args(ctx, ci, MODE_STEP);
+        a.fin.G = (int32_t)std::min<int64_t>(a.fin.G, p.nblocks);
+    }
     return a;
 }
 
@@ -1050,12 +1063,12 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
             int bcy = c.col[axis].cy, bb = c.col[axis].b;
             for (int cy : {4, 8, 16, 32, 64}) {
                 if (!col_has(ctx->prec, cy) || n % cy) continue;
-                for (int b = 1; b <= 64; b *= 2) {
+                for (int b = 1; b <= kColMaxThreads; b *= 2) {
                     ClassPlan t = c;
                     if (!planCol(t, ctx->prec, axis, cy, b)) continue;
-                    if (b * t.col[axis].P < 64 && b < 64 && c.nx % (2 * b) == 0 &&
-                        2 * b * t.col[axis].P <= kColMaxThreads)
-                        continue;  // a wider block is available
+                    ClassPlan wider = c;
+                    if (b * t.col[axis].P < 64 && planCol(wider, ctx->prec, axis, cy, 2 * b))
+                        continue;  // a wider block fills the wavefront better
                     ctx->classes[ci] = t;
                     fill_member_table(ctx);
                     if ((st = upload_tables(ctx)) != CH_OK) {

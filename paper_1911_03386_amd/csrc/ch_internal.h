@@ -12,7 +12,6 @@ constexpr int kWaveScanLevels = 6; // lanes of one line inside a wavefront: P <=
 constexpr int kSeriesSlots = 5;    // F(jK-1), F(jK), F(jK+1), <C>(jK), G_id(jK)
 constexpr int kPassAThreads = 256; // 4 wavefronts
 constexpr int kColMaxThreads = 512;
-constexpr int kHalo = 2;           // halo columns kept on each side of an LDS row
 
 // Coefficients of the periodic solve (I + rho [1,-4,6,-4,1]) y = x along one
 // axis of one member, factored as y = ikappa * Qa^{-1} Qc^{-1} x with the
@@ -45,18 +44,23 @@ struct MemberDev {
 enum : int { MODE_STEP = 0, MODE_DIAG = 1, MODE_TIMING = 2 };
 
 // Per-member reduction of the pass-A partial sums (F, sum C, sum |grad mu|^2)
-// into the sample series; run by block 0 of the last sweep of a step, or by
-// a one-block kernel after a diagnostics-only pass A.
+// into the sample series.  Blocks 0..G-1 of the step's last sweep do it
+// (block b takes members b, b+G, ...), or a G-block kernel after a
+// diagnostics-only pass A.  The step index comes from the stamp pass A wrote,
+// so the step counter itself is only read by pass A and advanced by one
+// thread of the last sweep.
 struct FinArgs {
     int32_t enabled;           // 0: nothing to do
-    int32_t mode;              // MODE_STEP: record what step n needs, then n -> n+1
-                               // MODE_DIAG: record everything, keep n
+    int32_t mode;              // MODE_STEP: record what step n needs; the last sweep then
+                               //   advances the counter.  MODE_DIAG: record everything.
+    int32_t G;                 // blocks taking part in the reduction
     const MemberDev* mem;
     const int32_t* mids;       // member ids of the class
     int32_t nmem;
     int32_t K;                 // cadence
     int64_t blocks_per_member; // pass-A blocks (= partial triples) per member
     const double* partials;    // [member][blocks_per_member][3]
+    const int64_t* nstamp;     // step index of the partials (written by pass A)
     int64_t max_samples;
     int64_t* step;             // step counter of the class
     double* series;            // [member][max_samples][kSeriesSlots]
@@ -83,6 +87,7 @@ struct PassAArgs {
     int32_t K;                 // cadence
     const int64_t* step;       // step counter of this class (read only)
     double* partials;          // [nblocks][3]
+    int64_t* nstamp;           // block 0 records the step index of the partials here
 };
 
 struct ColArgs {
@@ -118,5 +123,6 @@ hipError_t launch_beta(const double* series, int64_t max_samples, int32_t member
 bool passA_has(int dim, int cx, int rl);
 bool col_has(int prec, int cy);
 int passA_pad(int prec);       // LDS padding (elements) after every chunk
+int passA_halo(int prec);      // periodic halo columns on each side of an LDS row
 
 }  // namespace chk

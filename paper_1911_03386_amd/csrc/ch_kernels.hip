@@ -259,43 +259,60 @@ __device__ __forceinline__ void scan_bwd_wave(T (&e0)[RL], T (&e1)[RL], int j, i
     }
 }
 
-// Per-member reduction of the pass-A partials, in block order with Neumaier
-// compensation (deterministic), into the series; MODE_STEP then advances the
-// step counter.  Called by every thread of one block.
-__device__ void finalize(const FinArgs& f, int tid, int nthreads)
+// Per-member reduction of the pass-A partials into the series.  Each thread of
+// the block sums a strided subset of the member's partials (Neumaier), the
+// wavefronts reduce with a fixed shuffle tree and thread 0 combines the
+// wavefront sums in order: the result is deterministic.  blockDim.x must be a
+// multiple of 64 (<= 512).  Called by the whole block.
+__device__ void finalize_block(const FinArgs& f, int b, int G, double (*sred)[3])
 {
-    const int64_t n = *f.step;
+    const int tid = threadIdx.x, nthreads = blockDim.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t n = *f.nstamp;
     const int K = f.K;
     bool needF = true, needG = true;
     if (f.mode == MODE_STEP) {
         needG = (n % K) == 0;
         needF = needG || (n >= 1 && ((n - 1) % K) == 0) || (((n + 1) % K) == 0);
     }
-    if (needF) {
-        for (int ml = tid; ml < f.nmem; ml += nthreads) {
+    if (!needF) return;
+    for (int ml = b; ml < f.nmem; ml += G) {
+        double s[3] = {0.0, 0.0, 0.0}, cmp[3] = {0.0, 0.0, 0.0};
+        const double* pp = f.partials + (int64_t)ml * f.blocks_per_member * 3;
+        for (int64_t i = tid; i < f.blocks_per_member; i += nthreads) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const double x = pp[i * 3 + q];
+                const double t = s[q] + x;
+                cmp[q] += (fabs(s[q]) >= fabs(x)) ? (s[q] - t) + x : (x - t) + s[q];
+                s[q] = t;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) s[q] += cmp[q];
+        for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) s[q] += __shfl_down(s[q], off, 64);
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) sred[wave][q] = s[q];
+        __syncthreads();
+        if (tid == 0) {
+            double t[3] = {0.0, 0.0, 0.0};
+            for (int w = 0; w < nthreads / 64; ++w)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) t[q] += sred[w][q];
             const int gm = f.mids[ml];
             const MemberDev& mm = f.mem[gm];
-            double s[3] = {0.0, 0.0, 0.0}, cmp[3] = {0.0, 0.0, 0.0};
-            const double* pp = f.partials + (int64_t)ml * f.blocks_per_member * 3;
-            for (int64_t b = 0; b < f.blocks_per_member; ++b) {
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    const double x = pp[b * 3 + q];
-                    const double t = s[q] + x;
-                    cmp[q] += (fabs(s[q]) >= fabs(x)) ? (s[q] - t) + x : (x - t) + s[q];
-                    s[q] = t;
-                }
-            }
-            const double F = mm.vol * (s[0] + cmp[0]);
-            const double mC = (s[1] + cmp[1]) / (double)mm.sites;
-            const double G = -mm.vol * (s[2] + cmp[2]);
+            const double F = mm.vol * t[0];
+            const double mC = t[1] / (double)mm.sites;
+            const double Gid = -mm.vol * t[2];
             double* ser = f.series + (int64_t)gm * f.max_samples * kSeriesSlots;
             const int64_t ms = f.max_samples;
             if (n % K == 0 && n / K < ms) {
                 ser[(n / K) * kSeriesSlots + 1] = F;
                 if (needG) {
                     ser[(n / K) * kSeriesSlots + 3] = mC;
-                    ser[(n / K) * kSeriesSlots + 4] = G;
+                    ser[(n / K) * kSeriesSlots + 4] = Gid;
                 }
             }
             if (n >= 1 && (n - 1) % K == 0 && (n - 1) / K < ms) ser[((n - 1) / K) * kSeriesSlots + 2] = F;
@@ -304,17 +321,20 @@ __device__ void finalize(const FinArgs& f, int tid, int nthreads)
                 double* en = f.energy_now + (int64_t)gm * 4;
                 en[0] = F;
                 en[1] = mC;
-                en[2] = G;
+                en[2] = Gid;
                 en[3] = (double)n;
             }
             if (!isfinite(F)) f.flags[gm] = 1;
         }
+        __syncthreads();  // sred is reused by the next member
     }
-    __syncthreads();  // every thread has read n
-    if (tid == 0 && f.mode == MODE_STEP) *f.step = n + 1;
 }
 
-__global__ void fin_kernel(FinArgs f) { finalize(f, threadIdx.x, blockDim.x); }
+__global__ void __launch_bounds__(256) fin_kernel(FinArgs f)
+{
+    __shared__ double sred[4][3];
+    finalize_block(f, blockIdx.x, gridDim.x, sred);
+}
 
 template <typename T>
 struct Vec16;
@@ -360,6 +380,10 @@ __device__ __forceinline__ float4 vec_make<float>(const float* in)
 
 template <typename T>
 struct PadOf;
+// LDS row layout of pass A: HALO periodic halo columns on each side (the
+// 16-byte vector width, so a staged vector never straddles a chunk) and one
+// element of padding after every chunk of CX elements, so that the lanes of a
+// line, which read chunk-strided addresses, fall into different banks.
 template <>
 struct PadOf<double> {
     static constexpr int v = 1;
@@ -381,6 +405,8 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
 
     constexpr int PADE = PadOf<T>::v;
     constexpr int VEC = Vec16<T>::n;
+    constexpr int HALO = VEC;
+    static_assert(CX % VEC == 0, "LDS layout assumes vector-aligned chunks");
     using VT = typename Vec16<T>::type;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -416,43 +442,51 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     const int nrows = Ract + (needG ? 3 : 2);
     const int npl = (DIM == 3) ? (needG ? 4 : 3) : 1;
     {
-        // interior: 16-byte vector loads, one row segment per thread
+        // Items: per staged row, nx/VEC interior vectors plus one halo vector on
+        // each side.  Each thread issues a batch of loads before writing any of
+        // them to LDS, so the memory latency is paid once per batch.
         const int nvec = nx / VEC;
-        const int rpi = nvec >= nthreads ? 1 : nthreads / nvec;  // rows per sweep
-        const int r0 = nvec >= nthreads ? 0 : tid / nvec;
-        const int xv0 = nvec >= nthreads ? tid : tid - r0 * nvec;
-        const int xstep = nvec >= nthreads ? nthreads : nvec;
-        if (r0 < rpi) {
-            for (int pl = 0; pl < npl; ++pl) {
-                const int zz = (DIM == 3) ? wrapi(z - 1 + pl, nz) : 0;
-                T* dplane = sC + pl * planeStride;
-                for (int r = r0; r < nrows; r += rpi) {
-                    const int yy = wrapi(y0 - 1 + r, ny);
-                    const T* srow = C + ((int64_t)zz * ny + yy) * nx;
-                    T* drow = dplane + r * pitch;
-                    for (int xv = xv0; xv < nvec; xv += xstep) {
-                        T vals[VEC];
-                        vec_get<T>(*reinterpret_cast<const VT*>(srow + xv * VEC), vals);
+        const int W = nvec + 2;
+        int xi = tid % W, r = tid / W, pl = 0;
+        const int dxi = nthreads % W, drr = nthreads / W;
+        while (r >= nrows) {
+            r -= nrows;
+            ++pl;
+        }
+        constexpr int NB = 8;
+        while (pl < npl) {
+            VT val[NB];
+            int dst[NB];
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) {
-                            const int xx = xv * VEC + e + kHalo;
-                            drow[xx + (xx / CX) * PADE] = vals[e];
-                        }
-                    }
+            for (int i = 0; i < NB; ++i) {
+                dst[i] = -1;
+                if (pl < npl) {
+                    const int zz = (DIM == 3) ? wrapi(z - 1 + pl, nz) : 0;
+                    const int yy = wrapi(y0 - 1 + r, ny);
+                    const int xs = xi < nvec ? xi * VEC : (xi == nvec ? nx - HALO : 0);
+                    const int xx = xi < nvec ? xi * VEC + HALO : (xi == nvec ? 0 : nx + HALO);
+                    val[i] = *reinterpret_cast<const VT*>(C + ((int64_t)zz * ny + yy) * nx + xs);
+                    dst[i] = pl * planeStride + r * pitch + xx + (xx / CX) * PADE;
+                }
+                xi += dxi;
+                r += drr;
+                if (xi >= W) {
+                    xi -= W;
+                    ++r;
+                }
+                while (r >= nrows) {
+                    r -= nrows;
+                    ++pl;
                 }
             }
-        }
-        // periodic halo columns: 2 on each side of every staged row
-        const int nh = npl * nrows * 2 * kHalo;
-        for (int i = tid; i < nh; i += nthreads) {
-            const int h = i & (2 * kHalo - 1), rr = i >> 2;
-            const int pl = (DIM == 3) ? rr / nrows : 0, r = rr - pl * nrows;
-            const int zz = (DIM == 3) ? wrapi(z - 1 + pl, nz) : 0;
-            const int yy = wrapi(y0 - 1 + r, ny);
-            const int xs = h < kHalo ? nx - kHalo + h : h - kHalo;  // source column
-            const int xx = h < kHalo ? h : nx + h;                  // LDS column
-            sC[pl * planeStride + r * pitch + xx + (xx / CX) * PADE] =
-                C[((int64_t)zz * ny + yy) * nx + xs];
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+                if (dst[i] >= 0) {
+                    T e[VEC];
+                    vec_get<T>(val[i], e);
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) sC[dst[i] + q] = e[q];
+                }
         }
     }
     __syncthreads();
@@ -491,7 +525,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
         if (solve) {
 #pragma unroll
             for (int k = 0; k < CX; ++k) {
-                const int m0 = k + kHalo;
+                const int m0 = k + HALO;
                 // N = C^3 - C and the x second difference of C on lines -1 .. RL
                 T Nr[RL + 2], Dx[RL + 2];
 #pragma unroll
@@ -532,7 +566,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
                 if (!rowok[q]) continue;
 #pragma unroll
                 for (int k = 0; k < CX; ++k) {
-                    const int m0 = k + kHalo;
+                    const int m0 = k + HALO;
                     const double c = (double)AT(0, q, m0);
                     const double ex = (double)AT(0, q, m0 + 1) - c;
                     const double ey = (double)AT(0, q + 1, m0) - c;
@@ -564,7 +598,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
                 if (!rowok[q]) continue;
 #pragma unroll
                 for (int k = 0; k < CX; ++k) {
-                    const int m0 = k + kHalo;
+                    const int m0 = k + HALO;
                     const double mu = MU(0, q, m0);
                     const double gx = MU(0, q, m0 + 1) - mu;
                     const double gy = MU(0, q + 1, m0) - mu;
@@ -649,34 +683,41 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
             T* so = sC + (rl0 + q + 1) * pitch + j * (CX + PADE);  // plane slot 0 is free now
 #pragma unroll
             for (int k = 0; k < CX; ++k) {
-                const int m = k + kHalo;
+                const int m = k + HALO;
                 so[m + (m / CX) * PADE] = v[q][k];
             }
         }
         __syncthreads();
         const int nvec = nx / VEC;
-        const int rpi = nvec >= nthreads ? 1 : nthreads / nvec;
-        const int r0 = nvec >= nthreads ? 0 : tid / nvec;
-        const int xv0 = nvec >= nthreads ? tid : tid - r0 * nvec;
-        const int xstep = nvec >= nthreads ? nthreads : nvec;
-        if (r0 < rpi) {
-            for (int rr = r0; rr < Ract; rr += rpi) {
-                const T* srow = sC + (rr + 1) * pitch;
-                T* grow = Wout + ((int64_t)z * ny + y0 + rr) * nx;
-                for (int xv = xv0; xv < nvec; xv += xstep) {
-                    T vals[VEC];
+        int xv = tid % nvec, rr = tid / nvec;
+        const int dxv = nthreads % nvec, drr = nthreads / nvec;
+        constexpr int NB = 8;
+        while (rr < Ract) {
+            VT val[NB];
+            int64_t gdst[NB];
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) {
-                        const int xx = xv * VEC + e + kHalo;
-                        vals[e] = srow[xx + (xx / CX) * PADE];
-                    }
-                    *reinterpret_cast<VT*>(grow + xv * VEC) = vec_make<T>(vals);
+            for (int i = 0; i < NB; ++i) {
+                gdst[i] = -1;
+                if (rr < Ract) {
+                    const int xx = xv * VEC + HALO;
+                    val[i] = vec_make<T>(sC + (rr + 1) * pitch + xx + (xx / CX) * PADE);
+                    gdst[i] = ((int64_t)z * ny + y0 + rr) * nx + xv * VEC;
+                }
+                xv += dxv;
+                rr += drr;
+                if (xv >= nvec) {
+                    xv -= nvec;
+                    ++rr;
                 }
             }
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+                if (gdst[i] >= 0) *reinterpret_cast<VT*>(Wout + gdst[i]) = val[i];
         }
     }
 
     // ---- block partials of F, sum C, sum |grad mu|^2 (reduced by finalize) ----
+    if (blk == 0 && tid == 0 && a.mode != MODE_TIMING) *a.nstamp = n;
     if (needF && tid == 0) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         for (int w = 0; w < nthreads / 64; ++w) {
@@ -705,10 +746,15 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
     T* sS = sF1 + bP;  // chunk sums
     T* sM = sS + bP;   // line means
 
+    __shared__ double sred[kColMaxThreads / 64][3];
     const int tid = threadIdx.x;
-    const int j = tid / a.b;
-    const int c = tid - j * a.b;
     const int P = a.P;
+    // blockDim.x is b * P rounded up to whole wavefronts; threads beyond b * P
+    // only take part in the barriers
+    const int j0 = tid / a.b;
+    const bool colok = j0 < P;
+    const int j = colok ? j0 : 0;
+    const int c = tid - j0 * a.b;
     const int64_t blk = xcd_remap(blockIdx.x, a.nblocks);
     const int64_t bpm = a.cols / a.b;
     const int mloc = (int)(blk / bpm);
@@ -721,7 +767,7 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
 
     T v[CY];
 #pragma unroll
-    for (int k = 0; k < CY; ++k) v[k] = src[(int64_t)(j * CY + k) * st];
+    for (int k = 0; k < CY; ++k) v[k] = colok ? src[(int64_t)(j * CY + k) * st] : T(0);
 
     const AxisCoef& ac = md.ax[a.axis];
     const T a1 = (T)ac.a1, a2 = (T)ac.a2, ik = (T)ac.ikappa;
@@ -740,11 +786,13 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
 #pragma unroll
     for (int k = 0; k < CY; ++k) csum += v[k];
     fwd_zero(v, a1, a2, e0, e1);
-    sE0[j * a.b + c] = e0;
-    sE1[j * a.b + c] = e1;
-    sS[j * a.b + c] = csum;
+    if (colok) {
+        sE0[j * a.b + c] = e0;
+        sE1[j * a.b + c] = e1;
+        sS[j * a.b + c] = csum;
+    }
     __syncthreads();
-    if (j == 0) {
+    if (colok && j0 == 0) {
         T tot = T(0);
         for (int q = 0; q < P; ++q) tot += sS[q * a.b + c];
         const T mm = tot * (T)ac.inv_n;
@@ -771,10 +819,12 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
 
     // anti-causal recursion
     bwd_zero(v, a1, a2, e0, e1);
-    sF0[j * a.b + c] = e0;
-    sF1[j * a.b + c] = e1;
+    if (colok) {
+        sF0[j * a.b + c] = e0;
+        sF1[j * a.b + c] = e1;
+    }
     __syncthreads();
-    if (j == P - 1) {
+    if (colok && j0 == P - 1) {
         T z0 = T(0), z1 = T(0);
         for (int q = P - 1; q >= 0; --q) {
             mv(M, z0, z1);
@@ -794,12 +844,16 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
     __syncthreads();
     bwd_true(v, a1, a2, sF0[j * a.b + c], sF1[j * a.b + c], ik, m);
 
+    if (colok)
 #pragma unroll
-    for (int k = 0; k < CY; ++k) dst[(int64_t)(j * CY + k) * st] = v[k];
+        for (int k = 0; k < CY; ++k) dst[(int64_t)(j * CY + k) * st] = v[k];
 
-    // last sweep of the step: block 0 closes the step (the pass-A partials are
-    // complete, since pass A ran to the end before this launch)
-    if (a.fin.enabled && blockIdx.x == 0) finalize(a.fin, tid, blockDim.x);
+    // last sweep of the step: the first G blocks reduce the pass-A partials (pass
+    // A ran to completion before this launch) and one thread advances the step
+    if (a.fin.enabled) {
+        if ((int)blockIdx.x < a.fin.G) finalize_block(a.fin, blockIdx.x, a.fin.G, sred);
+        if (blockIdx.x == 0 && tid == 0 && a.fin.mode == MODE_STEP) *a.fin.step = *a.fin.nstamp + 1;
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -908,6 +962,7 @@ bool passA_has(int dim, int cx, int rl)
 }
 
 int passA_pad(int prec) { return prec == 0 ? PadOf<double>::v : PadOf<float>::v; }
+int passA_halo(int prec) { return prec == 0 ? Vec16<double>::n : Vec16<float>::n; }
 
 hipError_t launch_passA(int prec, int dim, int cx, int rl, const PassAArgs& a, size_t lds,
                         hipStream_t s)
@@ -924,7 +979,8 @@ template <typename T, int CY>
 static hipError_t launchC(const ColArgs& a, hipStream_t s)
 {
     const size_t lds = ((size_t)5 * a.b * a.P + a.b) * sizeof(T);
-    hipLaunchKernelGGL((col_kernel<T, CY>), dim3((unsigned)a.nblocks), dim3(a.b * a.P), lds, s, a);
+    const int threads = (a.b * a.P + 63) / 64 * 64;
+    hipLaunchKernelGGL((col_kernel<T, CY>), dim3((unsigned)a.nblocks), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
@@ -982,7 +1038,7 @@ hipError_t launch_reset(int64_t* steps, int nsteps, int64_t value, int32_t* flag
 
 hipError_t launch_fin(const FinArgs& f, hipStream_t s)
 {
-    hipLaunchKernelGGL(fin_kernel, dim3(1), dim3(256), 0, s, f);
+    hipLaunchKernelGGL(fin_kernel, dim3((unsigned)std::max(1, f.G)), dim3(256), 0, s, f);
     return hipGetLastError();
 }
 

@@ -283,3 +283,30 @@ def test_fp32_trajectory_error_short_window():
     assert err < 1e-4
     assert ferr < 1e-5
     assert drift < 1e-6
+
+
+def test_autotune_keeps_parity_and_caches(tmp_path):
+    descs = [make_desc((64, 32), 0.01, 1e-3, c0=0.0, noise=0.1, seed=31),
+             make_desc((16, 16, 8), 0.01, 5e-4, c0=0.2, noise=0.05, seed=32)]
+    cache = str(tmp_path / "tune.txt")
+    N = 20
+    ens = Ensemble(descs, prec=CH_F64, cadence=10, max_samples=N // 10 + 1)
+    ens.init_random()
+    ens.autotune(cache)
+    text = open(cache).read()
+    assert text.count("\n") == 2 and ":f64:2D:64x32x1:m1 " in text
+    plan = ens.describe()
+    ens.step(N)
+    for m, d in enumerate(descs):
+        shape = ens.shape(m)
+        ref = oracle.step(_ref_field(d, shape), d.gamma, d.dt, N, L=_L(d))
+        assert float(np.abs(ens.get_field(m) - ref).max()) <= TOL
+    ens.close()
+    # a second context takes the cached shapes without timing again
+    ens2 = Ensemble(descs, prec=CH_F64, cadence=10, max_samples=N // 10 + 1)
+    ens2.autotune(cache)
+    assert ens2.describe() == plan
+    ms = ens2.time_kernels(3)
+    assert ms[0] > 0 and ms[1] > 0 and ms[2] > 0
+    assert ens2.step_count == 3
+    ens2.close()
