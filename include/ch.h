@@ -156,15 +156,16 @@ ch_status ch_beta_series(ch_ctx* ctx, int32_t member, double* t, double* F, doub
 ch_status ch_autotune(ch_ctx* ctx, const char* cache_path);
 
 /* Number of size classes (members grouped by dimension and grid shape, in
- * order of first appearance) and explicit tile shapes for one class:
- * cx = elements per lane of an x-line and rl = x-lines per lane in the
- * RHS + x-solve pass, waves = wavefronts per block of that pass, cy/by =
- * elements per lane and columns per block of the y-solve, cz/bz the same for
- * the z-solve (ignored in 2D).  CH_EUNSUPPORTED if the shape is not valid for
- * the class (nothing changes then). */
+ * order of first appearance) and explicit tile shapes for one class.  The
+ * RHS + x-solve pass: cx = elements per lane of an x-line, rl = x-lines per
+ * lane, waves = wavefronts per block, units = z-planes of one y-band a 3D
+ * block walks through with a ring of staged planes (1 in 2D).  The y-solve: cy = elements per
+ * lane, by = columns per block; cz/bz the same for the z-solve (ignored in
+ * 2D).  CH_EUNSUPPORTED if the shape is not valid for the class (nothing
+ * changes then). */
 ch_status ch_num_classes(const ch_ctx* ctx, int32_t* nclasses);
-ch_status ch_set_tiles(ch_ctx* ctx, int32_t cls, int32_t cx, int32_t rl, int32_t waves, int32_t cy,
-                       int32_t by, int32_t cz, int32_t bz);
+ch_status ch_set_tiles(ch_ctx* ctx, int32_t cls, int32_t cx, int32_t rl, int32_t waves,
+                       int32_t units, int32_t cy, int32_t by, int32_t cz, int32_t bz);
 
 /* HIP graphs: with graph_steps > 0, ch_step replays a captured graph of
  * graph_steps steps (default 16); 0 launches every kernel directly.  Kernels

@@ -93,7 +93,7 @@ def load() -> ctypes.CDLL:
         "ch_solver_coefficients": (ctypes.c_int, [ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                                   ctypes.c_int32, dp]),
         "ch_num_classes": (ctypes.c_int, [vp, P(ctypes.c_int32)]),
-        "ch_set_tiles": (ctypes.c_int, [vp] + [ctypes.c_int32] * 8),
+        "ch_set_tiles": (ctypes.c_int, [vp] + [ctypes.c_int32] * 9),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -246,9 +246,9 @@ class Ensemble:
         _check(load().ch_num_classes(self.ctx, ctypes.byref(n)), self.ctx)
         return n.value
 
-    def set_tiles(self, cls: int, cx: int, rl: int, waves: int, cy: int, by: int, cz: int = 0,
-                  bz: int = 0):
-        _check(load().ch_set_tiles(self.ctx, cls, cx, rl, waves, cy, by, cz, bz), self.ctx)
+    def set_tiles(self, cls: int, cx: int, rl: int, waves: int, units: int, cy: int, by: int,
+                  cz: int = 0, bz: int = 0):
+        _check(load().ch_set_tiles(self.ctx, cls, cx, rl, waves, units, cy, by, cz, bz), self.ctx)
 
     def set_graph_steps(self, g: int):
         _check(load().ch_set_graph_steps(self.ctx, g), self.ctx)

@@ -46,7 +46,8 @@ struct ClassPlan {
     int dim = 2, nx = 0, ny = 0, nz = 1;
     std::vector<int> members;
     // pass A
-    int cx = 0, rl = 1, waves = 4, P = 0, rpw = 0, R = 0, bands = 0, pitch = 0;
+    int cx = 0, rl = 1, waves = 4, units = 1, P = 0, rpw = 0, R = 0, bands = 0, pitch = 0;
+    int64_t bpmA = 0;  // pass-A blocks per member
     int64_t nblocksA = 0;
     size_t ldsA = 0;
     ColPlan col[3];  // [1] = y, [2] = z
@@ -66,9 +67,9 @@ int elem_size(int prec) { return prec == 0 ? 8 : 4; }
 
 int lds_pos(int xx, int cx, int pad) { return xx + (xx / cx) * pad; }
 
-bool planA(ClassPlan& c, int prec, int cx, int rl, int waves)
+bool planA(ClassPlan& c, int prec, int cx, int rl, int waves, int units)
 {
-    if (!passA_has(c.dim, cx, rl) || c.nx % cx) return false;
+    if (!passA_has(c.dim, cx, rl, units) || c.nx % cx) return false;
     const int P = c.nx / cx;
     if (P < 1 || P > 64) return false;
     if (waves < 1 || waves > kPassAThreads / 64) return false;
@@ -80,16 +81,23 @@ bool planA(ClassPlan& c, int prec, int cx, int rl, int waves)
     const int planes = c.dim == 3 ? 4 : 1;
     const size_t lds = (size_t)planes * (R + 3) * pitch * elem_size(prec);
     if (lds > kLdsLimit) return false;
+    if (units > 1) {
+        // the plane a unit adds must fit the prefetch registers of the block
+        const int64_t items = (int64_t)(R + 3) * (c.nx / halo + 2);
+        if (items > (int64_t)kPrefetchVecs * 64 * waves) return false;
+    }
     c.cx = cx;
     c.rl = rl;
     c.waves = waves;
+    c.units = units;
     c.P = P;
     c.rpw = rpw;
     c.R = R;
     c.bands = (c.ny + R - 1) / R;
     c.pitch = pitch;
     c.ldsA = lds;
-    c.nblocksA = (int64_t)c.members.size() * c.nz * c.bands;
+    c.bpmA = (int64_t)c.bands * ((c.nz + units - 1) / units);
+    c.nblocksA = (int64_t)c.members.size() * c.bpmA;
     return true;
 }
 
@@ -123,9 +131,11 @@ bool default_A(ClassPlan& c, int prec)
 {
     const int prefs[][2] = {{16, 2}, {16, 1}, {8, 2}, {8, 1}, {32, 1}, {4, 2}, {4, 1}, {32, 2},
                             {64, 1}, {4, 4}, {8, 4}, {16, 4}};
+    const int units = c.dim == 3 ? 8 : 1;
     for (int waves : {4, 2, 1})
         for (auto& p : prefs)
-            if (planA(c, prec, p[0], p[1], waves)) return true;
+            if (planA(c, prec, p[0], p[1], waves, units) || planA(c, prec, p[0], p[1], waves, 1))
+                return true;
     return false;
 }
 
@@ -474,6 +484,8 @@ PassAArgs passA_args(ch_ctx* ctx, int ci, int mode)
     a.waves = c.waves;
     a.R = c.R;
     a.bands_y = c.bands;
+    a.units = c.units;
+    a.blocks_per_member = c.bpmA;
     a.nblocks = c.nblocksA;
     a.pitch = c.pitch;
     a.mode = mode;
@@ -495,7 +507,7 @@ FinArgs fin_args(ch_ctx* ctx, int ci, int mode)
     f.mids = reinterpret_cast<const int32_t*>(ctx->ws + c.off_mids);
     f.nmem = (int32_t)c.members.size();
     f.K = ctx->K;
-    f.blocks_per_member = (int64_t)c.nz * c.bands;
+    f.blocks_per_member = c.bpmA;
     f.partials = reinterpret_cast<const double*>(ctx->ws + c.off_partials);
     f.nstamp = ctx->d_nstamp() + ci;
     f.G = (int32_t)std::min<int64_t>(c.members.size(), 1024);
@@ -536,7 +548,7 @@ hipError_t launch_A(ch_ctx* ctx, int ci, int mode)
 {
     ClassPlan& c = ctx->classes[ci];
     PassAArgs a = passA_args(ctx, ci, mode);
-    return launch_passA(ctx->prec, c.dim, c.cx, c.rl, a, c.ldsA, ctx->stream);
+    return launch_passA(ctx->prec, c.dim, c.cx, c.rl, c.units, a, c.ldsA, ctx->stream);
 }
 
 // the column sweeps of one step: 2D  w -> C ;  3D  w -> w (y), w -> C (z)
@@ -628,9 +640,9 @@ std::string plan_text(const ch_ctx* ctx)
     char buf[320];
     for (const auto& c : ctx->classes) {
         snprintf(buf, sizeof buf,
-                 "%dD %dx%dx%d %s x%zu: A cx=%d rl=%d P=%d waves=%d R=%d blocks=%lld lds=%zu", c.dim,
-                 c.nx, c.ny, c.nz, ctx->prec ? "f32" : "f64", c.members.size(), c.cx, c.rl, c.P,
-                 c.waves, c.R, (long long)c.nblocksA, c.ldsA);
+                 "%dD %dx%dx%d %s x%zu: A cx=%d rl=%d P=%d waves=%d units=%d R=%d blocks=%lld lds=%zu",
+                 c.dim, c.nx, c.ny, c.nz, ctx->prec ? "f32" : "f64", c.members.size(), c.cx, c.rl, c.P,
+                 c.waves, c.units, c.R, (long long)c.nblocksA, c.ldsA);
         s += buf;
         for (int a = 1; a < c.dim; ++a) {
             snprintf(buf, sizeof buf, " | %c cy=%d P=%d b=%d blocks=%lld", a == 1 ? 'y' : 'z',
@@ -985,33 +997,40 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
 {
     ch_status st = check_ctx(ctx);
     if (st != CH_OK) return st;
-    // cached choices: one line per class "key cx rl waves cy_y b_y cy_z b_z"
+    // cached choices: one line per class "key cx rl waves units cy_y b_y cy_z b_z"
+    constexpr int NV = 8;
     std::map<std::string, std::vector<int>> cache;
     if (cache_path) {
         if (FILE* f = fopen(cache_path, "r")) {
             char key[256];
-            int v[7];
-            while (fscanf(f, "%255s %d %d %d %d %d %d %d", key, &v[0], &v[1], &v[2], &v[3], &v[4], &v[5],
-                          &v[6]) == 8)
-                cache[key] = std::vector<int>(v, v + 7);
+            int v[NV];
+            while (fscanf(f, "%255s %d %d %d %d %d %d %d %d", key, &v[0], &v[1], &v[2], &v[3], &v[4],
+                          &v[5], &v[6], &v[7]) == NV + 1)
+                cache[key] = std::vector<int>(v, v + NV);
             fclose(f);
         }
     }
     hipEvent_t e0, e1;
     HIPCHK(ctx, hipEventCreate(&e0));
     HIPCHK(ctx, hipEventCreate(&e1));
+    // best of 3 batches of 8 launches after 2 warm-up launches
     auto time_it = [&](auto&& launch, float& ms) -> hipError_t {
-        hipError_t e = launch();  // warm-up
-        if (e != hipSuccess) return e;
-        const int reps = 5;
-        if ((e = hipEventRecord(e0, ctx->stream)) != hipSuccess) return e;
-        for (int r = 0; r < reps; ++r)
+        hipError_t e;
+        for (int w = 0; w < 2; ++w)
             if ((e = launch()) != hipSuccess) return e;
-        if ((e = hipEventRecord(e1, ctx->stream)) != hipSuccess) return e;
-        if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
-        e = hipEventElapsedTime(&ms, e0, e1);
-        ms /= reps;
-        return e;
+        const int reps = 8;
+        ms = 1e30f;
+        for (int b = 0; b < 3; ++b) {
+            if ((e = hipEventRecord(e0, ctx->stream)) != hipSuccess) return e;
+            for (int r = 0; r < reps; ++r)
+                if ((e = launch()) != hipSuccess) return e;
+            if ((e = hipEventRecord(e1, ctx->stream)) != hipSuccess) return e;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+            float t = 0;
+            if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) return e;
+            ms = std::min(ms, t / reps);
+        }
+        return hipSuccess;
     };
     hipError_t err = hipSuccess;
     for (int ci = 0; ci < (int)ctx->classes.size() && err == hipSuccess; ++ci) {
@@ -1021,8 +1040,9 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
         if (hit != cache.end()) {
             const std::vector<int>& v = hit->second;
             ClassPlan t = c;
-            bool ok = planA(t, ctx->prec, v[0], v[1], v[2]) && planCol(t, ctx->prec, 1, v[3], v[4]) &&
-                      (c.dim == 2 || planCol(t, ctx->prec, 2, v[5], v[6]));
+            bool ok = planA(t, ctx->prec, v[0], v[1], v[2], v[3]) &&
+                      planCol(t, ctx->prec, 1, v[4], v[5]) &&
+                      (c.dim == 2 || planCol(t, ctx->prec, 2, v[6], v[7]));
             if (ok) {
                 c = t;
                 continue;
@@ -1030,31 +1050,38 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
         }
         // pass A candidates (timing mode: reads C, writes the scratch field)
         float best = 1e30f;
-        int bcx = c.cx, brl = c.rl, bw = c.waves;
+        int bcx = c.cx, brl = c.rl, bw = c.waves, bu = c.units;
+        const int unit_opts_2d[] = {1};
+        const int unit_opts_3d[] = {1, 4, 8, 16, 32};
+        const int* uo = c.dim == 3 ? unit_opts_3d : unit_opts_2d;
+        const int nuo = c.dim == 3 ? 5 : 1;
         for (int waves : {4, 2, 1})
             for (int rl : {1, 2, 4})
-                for (int cx : {4, 8, 16, 32, 64}) {
-                    ClassPlan t = c;
-                    if (!planA(t, ctx->prec, cx, rl, waves)) continue;
-                    ctx->classes[ci] = t;
-                    fill_member_table(ctx);
-                    if ((st = upload_tables(ctx)) != CH_OK) {
-                        ctx->classes[ci] = c;
-                        return st;
+                for (int cx : {4, 8, 16, 32, 64})
+                    for (int ui = 0; ui < nuo; ++ui) {
+                        const int units = uo[ui];
+                        ClassPlan t = c;
+                        if (!planA(t, ctx->prec, cx, rl, waves, units)) continue;
+                        ctx->classes[ci] = t;
+                        fill_member_table(ctx);
+                        if ((st = upload_tables(ctx)) != CH_OK) {
+                            ctx->classes[ci] = c;
+                            return st;
+                        }
+                        float ms = 0;
+                        err = time_it([&] { return launch_A(ctx, ci, MODE_TIMING); }, ms);
+                        if (err != hipSuccess) break;
+                        if (ms < best) {
+                            best = ms;
+                            bcx = cx;
+                            brl = rl;
+                            bw = waves;
+                            bu = units;
+                        }
                     }
-                    float ms = 0;
-                    err = time_it([&] { return launch_A(ctx, ci, MODE_TIMING); }, ms);
-                    if (err != hipSuccess) break;
-                    if (ms < best) {
-                        best = ms;
-                        bcx = cx;
-                        brl = rl;
-                        bw = waves;
-                    }
-                }
         ctx->classes[ci] = c;
         if (err != hipSuccess) break;
-        planA(c, ctx->prec, bcx, brl, bw);
+        planA(c, ctx->prec, bcx, brl, bw, bu);
         ctx->classes[ci] = c;
         // column sweeps, in place on the scratch field
         for (int axis = 1; axis < c.dim && err == hipSuccess; ++axis) {
@@ -1095,8 +1122,8 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
             planCol(c, ctx->prec, axis, bcy, bb);
             ctx->classes[ci] = c;
         }
-        cache[key] = {c.cx, c.rl, c.waves, c.col[1].cy, c.col[1].b, c.dim == 3 ? c.col[2].cy : 0,
-                      c.dim == 3 ? c.col[2].b : 0};
+        cache[key] = {c.cx, c.rl, c.waves, c.units, c.col[1].cy, c.col[1].b,
+                      c.dim == 3 ? c.col[2].cy : 0, c.dim == 3 ? c.col[2].b : 0};
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1108,8 +1135,9 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
     if (cache_path) {
         if (FILE* f = fopen(cache_path, "w")) {
             for (auto& kv : cache)
-                fprintf(f, "%s %d %d %d %d %d %d %d\n", kv.first.c_str(), kv.second[0], kv.second[1],
-                        kv.second[2], kv.second[3], kv.second[4], kv.second[5], kv.second[6]);
+                fprintf(f, "%s %d %d %d %d %d %d %d %d\n", kv.first.c_str(), kv.second[0], kv.second[1],
+                        kv.second[2], kv.second[3], kv.second[4], kv.second[5], kv.second[6],
+                        kv.second[7]);
             fclose(f);
         }
     }
@@ -1124,14 +1152,14 @@ ch_status ch_num_classes(const ch_ctx* ctx, int32_t* nclasses)
     return CH_OK;
 }
 
-ch_status ch_set_tiles(ch_ctx* ctx, int32_t cls, int32_t cx, int32_t rl, int32_t waves, int32_t cy,
-                       int32_t by, int32_t cz, int32_t bz)
+ch_status ch_set_tiles(ch_ctx* ctx, int32_t cls, int32_t cx, int32_t rl, int32_t waves,
+                       int32_t units, int32_t cy, int32_t by, int32_t cz, int32_t bz)
 {
     ch_status st = check_ctx(ctx);
     if (st != CH_OK) return st;
     if (cls < 0 || cls >= (int)ctx->classes.size()) return fail(ctx, CH_EINVAL, "bad class index");
     ClassPlan t = ctx->classes[cls];
-    if (!planA(t, ctx->prec, cx, rl, waves) || !planCol(t, ctx->prec, 1, cy, by) ||
+    if (!planA(t, ctx->prec, cx, rl, waves, units) || !planCol(t, ctx->prec, 1, cy, by) ||
         (t.dim == 3 && !planCol(t, ctx->prec, 2, cz, bz)))
         return fail(ctx, CH_EUNSUPPORTED, "tile shape not valid for class %d", cls);
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));

@@ -13,9 +13,12 @@
 //                 in 3D, the neighbouring z-planes) in LDS, forms the RHS in
 //                 registers (lane = contiguous chunk of one line), solves the
 //                 periodic pentadiagonal system of every x-line and writes w.
-//                 On cadence steps it also forms the FP64 partial sums of F,
-//                 sum C and the dF/dt identity, and the last block to finish
-//                 reduces them per member in a fixed order.
+//                 On cadence steps it also forms per-block FP64 partial sums
+//                 of F, sum C and the dF/dt identity; the first blocks of the
+//                 step's last line sweep reduce them per member in a fixed
+//                 order.
+//   passA_ring_kernel  the same for 3D, one block walking several z-planes of
+//                 a y-band through a ring of staged planes.
 //   col_kernel    y- or z-lines.  A block owns b adjacent columns; lane
 //                 (column, chunk) holds a contiguous chunk of one line in
 //                 registers, loads are coalesced across columns.
@@ -732,6 +735,331 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
 }
 
 // --------------------------------------------------------------------------
+// pass A, 3D, several z-planes per block
+// --------------------------------------------------------------------------
+// A block owns a y-band of R x-lines and walks `units` consecutive z-planes
+// of it.  LDS holds a ring of 4 staged planes, so every plane of the band is
+// read from memory once per block instead of three or four times.  While one
+// plane is computed, the rows of the plane the next one adds are loaded into
+// registers; they go to LDS once every read of the ring slot they replace is
+// done.  Results are stored from registers: each lane writes its contiguous
+// chunk, so the ring needs no output buffer.
+template <typename T, int CX, int RL>
+__global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* sC = reinterpret_cast<T*>(lds_raw);
+    __shared__ double red[kPassAThreads / 64][3];
+
+    constexpr int PADE = PadOf<T>::v;
+    constexpr int VEC = Vec16<T>::n;
+    constexpr int HALO = VEC;
+    constexpr int NPF = kPrefetchVecs;
+    static_assert(CX % VEC == 0, "LDS layout assumes vector-aligned chunks");
+    using VT = typename Vec16<T>::type;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nthreads = blockDim.x;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+
+    const int64_t blk = xcd_remap(blockIdx.x, a.nblocks);
+    const int64_t bpm = a.blocks_per_member;
+    const int mloc = (int)(blk / bpm);
+    const int64_t rem = blk - (int64_t)mloc * bpm;
+    const int band = (int)(rem % a.bands_y);
+    const int zbase = (int)(rem / a.bands_y) * a.units;
+    const int nunits = min(a.units, nz - zbase);
+    const int y0 = band * a.R;
+    const int Ract = min(a.R, ny - y0);
+    const int mid = a.mids[mloc];
+    const MemberDev& md = a.mem[mid];
+    const T* C = reinterpret_cast<const T*>(a.C) + md.off;
+    T* Wout = reinterpret_cast<T*>(a.W) + md.off;
+
+    const int64_t n = *a.step;
+    const int K = a.K;
+    bool needF = false, needG = false;
+    if (a.mode == MODE_STEP) {
+        needG = (n % K) == 0;
+        needF = needG || (n >= 1 && ((n - 1) % K) == 0) || (((n + 1) % K) == 0);
+    } else if (a.mode == MODE_DIAG) {
+        needF = needG = true;
+    }
+    const bool solve = (a.mode != MODE_DIAG);
+
+    const int pitch = a.pitch;
+    const int planeStride = (a.R + 3) * pitch;
+    const int nvec = nx / VEC;
+    const int W = nvec + 2;                  // vectors per staged row: interior + 2 halo
+    const int nrows = Ract + (needG ? 3 : 2);
+    const int xhi = needG ? 2 : 1;           // highest plane offset the stencils read
+
+    // vector xi of staged row r of plane zz (the two halo vectors come last)
+    auto load_item = [&](int r, int xi, int zz, VT& val, int& dst) {
+        const int yy = wrapi(y0 - 1 + r, ny);
+        const int zw = wrapi(zz, nz);
+        const int xs = xi < nvec ? xi * VEC : (xi == nvec ? nx - HALO : 0);
+        const int xx = xi < nvec ? xi * VEC + HALO : (xi == nvec ? 0 : nx + HALO);
+        val = *reinterpret_cast<const VT*>(C + ((int64_t)zw * ny + yy) * nx + xs);
+        dst = ((zz - zbase + 1) & 3) * planeStride + r * pitch + xx + (xx / CX) * PADE;
+    };
+    auto put = [&](const VT& val, int dst) {
+        T e[VEC];
+        vec_get<T>(val, e);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) sC[dst + q] = e[q];
+    };
+
+    // Items (row, vector) of a plane are dealt to the threads round-robin:
+    // thread t takes items t, t + nthreads, ...; a cursor (r, xi) steps
+    // through them without divisions.
+    const int dxi = nthreads % W, dr = nthreads / W;
+    const int r_first = tid / W, xi_first = tid - r_first * W;
+    auto step_item = [&](int& r, int& xi) {
+        xi += dxi;
+        r += dr;
+        if (xi >= W) {
+            xi -= W;
+            ++r;
+        }
+    };
+    // first unit: planes zbase-1 .. zbase+xhi, in batches of NPF loads
+    for (int p = 0; p < xhi + 2; ++p) {
+        int r = r_first, xi = xi_first;
+        while (r < nrows) {
+            VT pv[NPF];
+            int pd[NPF];
+#pragma unroll
+            for (int i = 0; i < NPF; ++i) {
+                pd[i] = -1;
+                if (r < nrows) load_item(r, xi, zbase - 1 + p, pv[i], pd[i]);
+                step_item(r, xi);
+            }
+#pragma unroll
+            for (int i = 0; i < NPF; ++i)
+                if (pd[i] >= 0) put(pv[i], pd[i]);
+        }
+    }
+    __syncthreads();
+
+    const int P = a.P;
+    const int g = lane / P;
+    const int j = lane - g * P;
+    const int groups = a.rows_per_wave / RL;
+    const int rl0 = (wave * groups + g) * RL;
+    const bool lane_ok = g < groups;
+    bool rowok[RL];
+#pragma unroll
+    for (int q = 0; q < RL; ++q) rowok[q] = lane_ok && (rl0 + q < Ract);
+    const bool active = rowok[0];
+    const int cb_off = (rl0 + 1) * pitch + j * (CX + PADE);
+
+    const T ihx2 = (T)md.ih2[0], ihy2 = (T)md.ih2[1], ihz2 = (T)md.ih2[2];
+    const T dt = (T)md.dt, tg = (T)(2.0 * md.gamma * md.dt);
+    const T cxy = (T)(md.ih2[0] * md.ih2[1]);
+    const T cxz = (T)(md.ih2[0] * md.ih2[2]), cyz = (T)(md.ih2[1] * md.ih2[2]);
+
+    double pF = 0.0, pS = 0.0, pG = 0.0;
+    for (int u = 0; u < nunits; ++u) {
+        const int z = zbase + u;
+        const bool has_next = u + 1 < nunits;
+        // rows of the plane the next unit adds start loading now (the host
+        // guarantees one plane fits NPF vectors per thread)
+        VT pv[NPF];
+        int pd[NPF];
+        {
+            int r = r_first, xi = xi_first;
+#pragma unroll
+            for (int i = 0; i < NPF; ++i) {
+                pd[i] = -1;
+                if (has_next && r < nrows) load_item(r, xi, z + 1 + xhi, pv[i], pd[i]);
+                step_item(r, xi);
+            }
+        }
+
+        // ring slots of planes z-1 .. z+2
+        const int s0 = (u & 3) * planeStride + cb_off;
+        const int s1 = ((u + 1) & 3) * planeStride + cb_off;
+        const int s2 = ((u + 2) & 3) * planeStride + cb_off;
+        const int s3 = ((u + 3) & 3) * planeStride + cb_off;
+#define AT(dz, dy, m) \
+    sC[((dz) < 0 ? s0 : (dz) == 0 ? s1 : (dz) == 1 ? s2 : s3) + (dy) * pitch + (m) + ((m) / CX) * PADE]
+
+        T v[RL][CX];
+#pragma unroll
+        for (int q = 0; q < RL; ++q)
+#pragma unroll
+            for (int k = 0; k < CX; ++k) v[q][k] = T(0);
+
+        if (active) {
+            if (solve) {
+#pragma unroll
+                for (int k = 0; k < CX; ++k) {
+                    const int m0 = k + HALO;
+                    T Nr[RL + 2], Dx[RL + 2];
+#pragma unroll
+                    for (int q = 0; q < RL + 2; ++q) {
+                        const T c = AT(0, q - 1, m0);
+                        Nr[q] = c * c * c - c;
+                        Dx[q] = AT(0, q - 1, m0 + 1) - T(2) * c + AT(0, q - 1, m0 - 1);
+                    }
+#pragma unroll
+                    for (int q = 0; q < RL; ++q) {
+                        const T c = AT(0, q, m0), cw = AT(0, q, m0 - 1), ce = AT(0, q, m0 + 1);
+                        const T Nw = cw * cw * cw - cw, Ne = ce * ce * ce - ce;
+                        const T Nc = Nr[q + 1];
+                        T lapN = (Ne - T(2) * Nc + Nw) * ihx2 + (Nr[q + 2] - T(2) * Nc + Nr[q]) * ihy2;
+                        T cross = (Dx[q + 2] - T(2) * Dx[q + 1] + Dx[q]) * cxy;
+                        const T cu = AT(1, q, m0), cd = AT(-1, q, m0);
+                        const T Nu = cu * cu * cu - cu, Nd = cd * cd * cd - cd;
+                        lapN += (Nu - T(2) * Nc + Nd) * ihz2;
+                        const T dxxu = AT(1, q, m0 + 1) - T(2) * cu + AT(1, q, m0 - 1);
+                        const T dxxd = AT(-1, q, m0 + 1) - T(2) * cd + AT(-1, q, m0 - 1);
+                        cross += (dxxu - T(2) * Dx[q + 1] + dxxd) * cxz;
+                        const T dyy0 = AT(0, q + 1, m0) - T(2) * c + AT(0, q - 1, m0);
+                        const T dyyu = AT(1, q + 1, m0) - T(2) * cu + AT(1, q - 1, m0);
+                        const T dyyd = AT(-1, q + 1, m0) - T(2) * cd + AT(-1, q - 1, m0);
+                        cross += (dyyu - T(2) * dyy0 + dyyd) * cyz;
+                        v[q][k] = c + dt * lapN - tg * cross;
+                    }
+                }
+            }
+            if (needF) {
+                const double cbulk = a.conv ? 0.5 : 0.25;
+                const double hg = 0.5 * md.gamma;
+                const double dx2 = md.ih2[0], dy2 = md.ih2[1], dz2 = md.ih2[2];
+#pragma unroll
+                for (int q = 0; q < RL; ++q) {
+                    if (!rowok[q]) continue;
+#pragma unroll
+                    for (int k = 0; k < CX; ++k) {
+                        const int m0 = k + HALO;
+                        const double c = (double)AT(0, q, m0);
+                        const double ex = (double)AT(0, q, m0 + 1) - c;
+                        const double ey = (double)AT(0, q + 1, m0) - c;
+                        const double ez = (double)AT(1, q, m0) - c;
+                        const double gr = ex * ex * dx2 + ey * ey * dy2 + ez * ez * dz2;
+                        const double qq = c * c - 1.0;
+                        pF += cbulk * qq * qq + hg * gr;
+                        pS += c;
+                    }
+                }
+            }
+            if (needG) {
+                const double gam = md.gamma;
+                const double dx2 = md.ih2[0], dy2 = md.ih2[1], dz2 = md.ih2[2];
+                auto MU = [&](int dz, int dy, int m) -> double {
+                    const double uu = (double)AT(dz, dy, m);
+                    const double l =
+                        ((double)AT(dz, dy, m + 1) - 2.0 * uu + (double)AT(dz, dy, m - 1)) * dx2 +
+                        ((double)AT(dz, dy + 1, m) - 2.0 * uu + (double)AT(dz, dy - 1, m)) * dy2 +
+                        ((double)AT(dz + 1, dy, m) - 2.0 * uu + (double)AT(dz - 1, dy, m)) * dz2;
+                    return uu * uu * uu - uu - gam * l;
+                };
+#pragma unroll
+                for (int q = 0; q < RL; ++q) {
+                    if (!rowok[q]) continue;
+#pragma unroll
+                    for (int k = 0; k < CX; ++k) {
+                        const int m0 = k + HALO;
+                        const double mu = MU(0, q, m0);
+                        const double gx = MU(0, q, m0 + 1) - mu;
+                        const double gy = MU(0, q + 1, m0) - mu;
+                        const double gz = MU(1, q, m0) - mu;
+                        pG += gx * gx * dx2 + gy * gy * dy2 + gz * gz * dz2;
+                    }
+                }
+            }
+        }
+#undef AT
+
+        if (solve) {
+            LineCoef<T> cf;
+            load_coef(cf, md.ax[0], P);
+            ScanLanes SL;
+            make_lanes(SL, lane, g * P, P);
+            T mean[RL], csum[RL];
+#pragma unroll
+            for (int q = 0; q < RL; ++q) {
+                csum[q] = T(0);
+#pragma unroll
+                for (int k = 0; k < CX; ++k) csum[q] += v[q][k];
+            }
+#pragma unroll
+            for (int s = 0; s < kWaveScanLevels; ++s) {
+                const int d = 1 << s;
+                if (d < P) {
+#pragma unroll
+                    for (int q = 0; q < RL; ++q) {
+                        const T y = lane_get(SL.up[s], csum[q]);
+                        if (j >= d) csum[q] += y;
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < RL; ++q) {
+                mean[q] = lane_get(SL.last, csum[q]) * (T)md.ax[0].inv_n;
+#pragma unroll
+                for (int k = 0; k < CX; ++k) v[q][k] -= mean[q];
+            }
+            T e0[RL], e1[RL];
+#pragma unroll
+            for (int q = 0; q < RL; ++q) fwd_zero(v[q], cf.a1, cf.a2, e0[q], e1[q]);
+            scan_fwd_wave<T, RL>(e0, e1, j, P, SL, cf);
+#pragma unroll
+            for (int q = 0; q < RL; ++q) fwd_true(v[q], cf.a1, cf.a2, e0[q], e1[q], T(0));
+#pragma unroll
+            for (int q = 0; q < RL; ++q) bwd_zero(v[q], cf.a1, cf.a2, e0[q], e1[q]);
+            scan_bwd_wave<T, RL>(e0, e1, j, P, SL, cf);
+#pragma unroll
+            for (int q = 0; q < RL; ++q) bwd_true(v[q], cf.a1, cf.a2, e0[q], e1[q], cf.ik, mean[q]);
+            // each lane stores its own chunk of every line it holds
+#pragma unroll
+            for (int q = 0; q < RL; ++q) {
+                if (!rowok[q]) continue;
+                T* dst = Wout + ((int64_t)z * ny + y0 + rl0 + q) * nx + j * CX;
+#pragma unroll
+                for (int k = 0; k < CX; k += VEC)
+                    *reinterpret_cast<VT*>(dst + k) = vec_make<T>(&v[q][k]);
+            }
+        }
+
+        if (has_next) {
+            __syncthreads();  // every read of the slot the new plane replaces is done
+#pragma unroll
+            for (int i = 0; i < NPF; ++i)
+                if (pd[i] >= 0) put(pv[i], pd[i]);
+            __syncthreads();
+        }
+    }
+
+    if (blk == 0 && tid == 0 && a.mode != MODE_TIMING) *a.nstamp = n;
+    if (needF) {
+        for (int off = 32; off > 0; off >>= 1) {
+            pF += __shfl_down(pF, off, 64);
+            pS += __shfl_down(pS, off, 64);
+            pG += __shfl_down(pG, off, 64);
+        }
+        if (lane == 0) {
+            red[wave][0] = pF;
+            red[wave][1] = pS;
+            red[wave][2] = pG;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int w = 0; w < nthreads / 64; ++w) {
+                s0 += red[w][0];
+                s1 += red[w][1];
+                s2 += red[w][2];
+            }
+            a.partials[blk * 3 + 0] = s0;
+            a.partials[blk * 3 + 1] = s1;
+            a.partials[blk * 3 + 2] = s2;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
 // y- / z-line solves
 // --------------------------------------------------------------------------
 template <typename T, int CY>
@@ -937,13 +1265,37 @@ static hipError_t launchA(const PassAArgs& a, size_t lds, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T, int CX, int RL>
+static hipError_t launchRing(const PassAArgs& a, size_t lds, hipStream_t s)
+{
+    auto k = passA_ring_kernel<T, CX, RL>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k, dim3((unsigned)a.nblocks), dim3(64 * a.waves), lds, s, a);
+    return hipGetLastError();
+}
+
 // (chunk length, lines per lane) pairs that are compiled
 #define CH_PASSA_SHAPES(X) \
     X(4, 1) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(4, 2) X(8, 2) X(16, 2) X(32, 2) X(4, 4) X(8, 4) X(16, 4)
+// ... and those of the 3D plane-ring variant
+#define CH_RING_SHAPES(X) X(4, 1) X(8, 1) X(16, 1) X(32, 1) X(4, 2) X(8, 2) X(16, 2)
 
 template <typename T, int DIM>
-static hipError_t launchA_shape(int cx, int rl, const PassAArgs& a, size_t lds, hipStream_t s)
+static hipError_t launchA_shape(int cx, int rl, int units, const PassAArgs& a, size_t lds,
+                                hipStream_t s)
 {
+    if (DIM == 3 && units > 1) {
+#define X(C, R) \
+    if (cx == C && rl == R) return launchRing<T, C, R>(a, lds, s);
+        CH_RING_SHAPES(X)
+#undef X
+        return hipErrorInvalidValue;
+    }
+    if (units != 1) return hipErrorInvalidValue;
 #define X(C, R) \
     if (cx == C && rl == R) return launchA<T, DIM, C, R>(a, lds, s);
     CH_PASSA_SHAPES(X)
@@ -951,9 +1303,18 @@ static hipError_t launchA_shape(int cx, int rl, const PassAArgs& a, size_t lds, 
     return hipErrorInvalidValue;
 }
 
-bool passA_has(int dim, int cx, int rl)
+bool passA_has(int dim, int cx, int rl, int units)
 {
     if (dim != 2 && dim != 3) return false;
+    if (units > 1) {
+        if (dim != 3) return false;
+#define X(C, R) \
+    if (cx == C && rl == R) return true;
+        CH_RING_SHAPES(X)
+#undef X
+        return false;
+    }
+    if (units != 1) return false;
 #define X(C, R) \
     if (cx == C && rl == R) return true;
     CH_PASSA_SHAPES(X)
@@ -964,15 +1325,15 @@ bool passA_has(int dim, int cx, int rl)
 int passA_pad(int prec) { return prec == 0 ? PadOf<double>::v : PadOf<float>::v; }
 int passA_halo(int prec) { return prec == 0 ? Vec16<double>::n : Vec16<float>::n; }
 
-hipError_t launch_passA(int prec, int dim, int cx, int rl, const PassAArgs& a, size_t lds,
-                        hipStream_t s)
+hipError_t launch_passA(int prec, int dim, int cx, int rl, int units, const PassAArgs& a,
+                        size_t lds, hipStream_t s)
 {
     if (a.nblocks <= 0) return hipSuccess;
     if (prec == 0)
-        return dim == 2 ? launchA_shape<double, 2>(cx, rl, a, lds, s)
-                        : launchA_shape<double, 3>(cx, rl, a, lds, s);
-    return dim == 2 ? launchA_shape<float, 2>(cx, rl, a, lds, s)
-                    : launchA_shape<float, 3>(cx, rl, a, lds, s);
+        return dim == 2 ? launchA_shape<double, 2>(cx, rl, units, a, lds, s)
+                        : launchA_shape<double, 3>(cx, rl, units, a, lds, s);
+    return dim == 2 ? launchA_shape<float, 2>(cx, rl, units, a, lds, s)
+                    : launchA_shape<float, 3>(cx, rl, units, a, lds, s);
 }
 
 template <typename T, int CY>

@@ -131,7 +131,7 @@ def _all_tiles(ens, cls, n, prec):
                 P = ny // cy
                 for b in (1, 2, 4, 8, 16, 32, 64):
                     if nx % b == 0 and b * P <= 512:
-                        out.append((cx, rl, waves, cy, b))
+                        out.append((cx, rl, waves, 1, cy, b))
     return out
 
 
@@ -142,17 +142,20 @@ def test_every_tile_shape_parity_2d():
     Cref = oracle.step(_ref_field(d, (64, 128)), gamma, dt, N)
     ens = Ensemble([d], prec=CH_F64, cadence=5, max_samples=N // 5 + 1)
     tried = 0
-    for cx, rl, waves, cy, b in _all_tiles(ens, 0, n, CH_F64):
+    for cx, rl, waves, units, cy, b in _all_tiles(ens, 0, n, CH_F64):
         try:
-            ens.set_tiles(0, cx, rl, waves, cy, b)
+            ens.set_tiles(0, cx, rl, waves, units, cy, b)
         except ChError:
             continue
         ens.init_random()
         ens.step(N)
         err = float(np.abs(ens.get_field(0) - Cref).max())
-        assert err <= TOL, ((cx, rl, waves, cy, b), err)
+        assert err <= TOL, ((cx, rl, waves, units, cy, b), err)
         tried += 1
-    assert tried >= 40
+    assert tried >= 80
+    # several planes per block is a 3D-only variant
+    with pytest.raises(ChError):
+        ens.set_tiles(0, 16, 1, 4, 2, 8, 8)
     ens.close()
 
 
@@ -161,24 +164,55 @@ def test_every_tile_shape_parity_3d():
     d = make_desc(n, gamma, dt, c0=0.0, noise=0.1, seed=22)
     N = 6
     Cref = oracle.step(_ref_field(d, (24, 16, 32)), gamma, dt, N)
+    _, S = oracle.run_series(_ref_field(d, (24, 16, 32)), gamma, dt, N, K=5)
     ens = Ensemble([d], prec=CH_F64, cadence=5, max_samples=N // 5 + 1)
     tried = 0
+    seen_units = set()
     for cx, rl in ((4, 1), (8, 1), (16, 1), (32, 1), (4, 2), (8, 2), (16, 2), (4, 4), (8, 4)):
         for waves in (1, 4):
-            for cy, by in ((4, 8), (8, 32), (16, 2)):
-                for cz, bz in ((4, 32), (8, 16), (24 // 4, 1)):
-                    if 24 % cz:
-                        continue
-                    try:
-                        ens.set_tiles(0, cx, rl, waves, cy, by, cz, bz)
-                    except ChError:
-                        continue
-                    ens.init_random()
-                    ens.step(N)
-                    err = float(np.abs(ens.get_field(0) - Cref).max())
-                    assert err <= TOL, ((cx, rl, waves, cy, by, cz, bz), err)
-                    tried += 1
-    assert tried >= 16
+            for units in (1, 3, 8, 24):
+                for cy, by in ((4, 8), (8, 32), (16, 2)):
+                    for cz, bz in ((4, 32), (8, 16), (24 // 4, 1), (8, 64)):
+                        if 24 % cz:
+                            continue
+                        try:
+                            ens.set_tiles(0, cx, rl, waves, units, cy, by, cz, bz)
+                        except ChError:
+                            continue
+                        ens.init_random()
+                        ens.step(N)
+                        err = float(np.abs(ens.get_field(0) - Cref).max())
+                        assert err <= TOL, ((cx, rl, waves, units, cy, by, cz, bz), err)
+                        _check_series(ens.beta_series(0), S)
+                        tried += 1
+                        seen_units.add(units)
+    assert tried >= 40 and seen_units == {1, 3, 8, 24}
+    ens.close()
+
+
+def test_plane_ring_fp32_3d():
+    """FP32 bulk, 3D, several z-planes per block (ragged last unit: 20 planes
+    in units of 8) against the oracle from the same FP32-rounded field."""
+    n, gamma, dt = (64, 24, 20), 0.01, 5e-4
+    d = make_desc(n, gamma, dt, c0=0.1, noise=0.1, seed=23)
+    N = 6
+    C0 = _ref_field(d, (20, 24, 64)).astype(np.float32).astype(np.float64)
+    Cref = oracle.step(C0, gamma, dt, N)
+    ens = Ensemble([d], prec=CH_F32_BULK, cadence=5, max_samples=N // 5 + 1)
+    tried = 0
+    for cx, rl in ((4, 1), (8, 1), (16, 1), (32, 1), (4, 2), (8, 2), (16, 2)):
+        for waves in (1, 2, 4):
+            try:
+                ens.set_tiles(0, cx, rl, waves, 8, 8, 8, 4, 16)
+            except ChError:
+                continue
+            ens.init_random()
+            ens.step(N)
+            err = float(np.abs(ens.get_field(0) - Cref).max())
+            assert err <= 2e-5, ((cx, rl, waves), err)
+            tried += 1
+    assert tried >= 10
+    ens.close()
 
 
 def test_graph_and_eager_bitwise_equal_and_deterministic():
