@@ -35,7 +35,8 @@ def parse():
     p.add_argument("--workload", default="c3")
     p.add_argument("--compare", default="c2", help="second workload reported in the same line ('' = none)")
     p.add_argument("--compare-steps", type=int, default=None)
-    p.add_argument("--kernel-steps", type=int, default=50, help="directly launched steps timed per kernel")
+    p.add_argument("--kernel-steps", type=int, default=200,
+                   help="real steps after the timed region whose kernels are timed one by one")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-autotune", dest="autotune", action="store_false",
@@ -212,7 +213,7 @@ def main():
             "ms_per_step": rc["gpu_ms"] / csteps,
             "ms_per_launch": {k: round(v, 5) for k, v in zip(kinds, rc["kernel_ms"])},
             "hbm_frac_of_step": round(wc.sites * 4 * wordc * (1.5 if wc.descs[0].dim == 3 else 1.0)
-                                      / (rc["gpu_ms"] / args.compare_steps / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+                                      / (rc["gpu_ms"] / csteps / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
             "fp32_batched_over_this": round(value / vc, 2),
         }
     if not args.no_cpu_baseline:

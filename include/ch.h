@@ -176,10 +176,13 @@ ch_status ch_set_graph_steps(ch_ctx* ctx, int32_t graph_steps);
 /* Describe the chosen tile shapes as text (for logs), NUL-terminated. */
 ch_status ch_describe(const ch_ctx* ctx, char* buf, size_t cap);
 
-/* Mean device duration (ms) per launch of each kernel kind over nsteps
- * directly launched steps, bracketed by HIP events on the context stream:
- * ms[0] = RHS + x-solve pass, ms[1] = y-solve pass, ms[2] = z-solve pass (0 in
- * 2D), summed over size classes.  The state advances by nsteps. */
+/* Mean device duration (ms) per launch of each kernel kind over nsteps real
+ * steps, launched directly on the context stream, each kernel with a pair of
+ * HIP events that take its own start and end timestamps
+ * (hipExtLaunchKernel): ms[0] = RHS + x-solve pass, ms[1] = y-solve pass,
+ * ms[2] = z-solve pass (0 in 2D), summed over size classes.  The steps include
+ * the sample-step diagnostics like any other steps; the state advances by
+ * nsteps. */
 ch_status ch_time_kernels(ch_ctx* ctx, int64_t nsteps, double* ms);
 
 /* Release the context (synchronises its stream).  Later calls with the same

@@ -82,9 +82,13 @@ bool planA(ClassPlan& c, int prec, int cx, int rl, int waves, int units)
     const size_t lds = (size_t)planes * (R + 3) * pitch * elem_size(prec);
     if (lds > kLdsLimit) return false;
     if (units > 1) {
-        // the plane a unit adds must fit the prefetch registers of the block
-        const int64_t items = (int64_t)(R + 3) * (c.nx / halo + 2);
-        if (items > (int64_t)kPrefetchVecs * 64 * waves) return false;
+        // a wavefront's share of the plane a unit adds must fit the prefetch
+        // registers (rows round-robin over wavefronts, 64-vector segments per
+        // row), and the halo vectors one per thread
+        const int rows = R + 3;
+        const int nseg = (c.nx / halo + 63) / 64;
+        if ((rows + waves - 1) / waves * nseg > kPrefetchVecs) return false;
+        if (2 * rows > 64 * waves) return false;
     }
     c.cx = cx;
     c.rl = rl;
@@ -544,22 +548,23 @@ ColArgs col_args(ch_ctx* ctx, int ci, int axis, const void* src, void* dst, bool
     return a;
 }
 
-hipError_t launch_A(ch_ctx* ctx, int ci, int mode)
+hipError_t launch_A(ch_ctx* ctx, int ci, int mode, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
     ClassPlan& c = ctx->classes[ci];
     PassAArgs a = passA_args(ctx, ci, mode);
-    return launch_passA(ctx->prec, c.dim, c.cx, c.rl, c.units, a, c.ldsA, ctx->stream);
+    return launch_passA(ctx->prec, c.dim, c.cx, c.rl, c.units, a, c.ldsA, ctx->stream, ev0, ev1);
 }
 
 // the column sweeps of one step: 2D  w -> C ;  3D  w -> w (y), w -> C (z)
-hipError_t launch_cols(ch_ctx* ctx, int ci, int axis)
+hipError_t launch_cols(ch_ctx* ctx, int ci, int axis, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr)
 {
     ClassPlan& c = ctx->classes[ci];
     void* W = ctx->d_W();
     void* C = ctx->d_C();
     const bool last = (axis == c.dim - 1);
     return launch_col(ctx->prec, c.col[axis].cy, col_args(ctx, ci, axis, W, last ? C : W, last),
-                      ctx->stream);
+                      ctx->stream, ev0, ev1);
 }
 
 hipError_t enqueue_step(ch_ctx* ctx)
@@ -961,30 +966,30 @@ ch_status ch_time_kernels(ch_ctx* ctx, int64_t nsteps, double* ms)
     if (nsteps < 1 || !ms) return fail(ctx, CH_EINVAL, "nsteps >= 1 and ms required");
     if ((ctx->step + nsteps) / ctx->K >= ctx->max_samples)
         return fail(ctx, CH_ESTATE, "sample capacity exceeded");
+    // real steps, launched directly; every kernel carries a pair of events
+    // that take its own start and end timestamps
     const int nc = (int)ctx->classes.size();
-    std::vector<hipEvent_t> ev(4 * (size_t)nsteps, nullptr);
-    for (auto& e : ev) HIPCHK(ctx, hipEventCreate(&e));
+    std::vector<hipEvent_t> ev(2 * 3 * (size_t)nc * nsteps, nullptr);
+    for (auto& x : ev) HIPCHK(ctx, hipEventCreate(&x));
+    auto E = [&](int64_t s, int ci, int k) { return &ev[2 * ((size_t)(s * nc + ci) * 3 + k)]; };
     hipError_t e = hipSuccess;
     for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
-        hipEvent_t* E = &ev[4 * s];
-        e = hipEventRecord(E[0], ctx->stream);
-        for (int ci = 0; ci < nc && e == hipSuccess; ++ci) e = launch_A(ctx, ci, MODE_STEP);
-        if (e == hipSuccess) e = hipEventRecord(E[1], ctx->stream);
-        for (int ci = 0; ci < nc && e == hipSuccess; ++ci) e = launch_cols(ctx, ci, 1);
-        if (e == hipSuccess) e = hipEventRecord(E[2], ctx->stream);
         for (int ci = 0; ci < nc && e == hipSuccess; ++ci)
-            if (ctx->classes[ci].dim == 3) e = launch_cols(ctx, ci, 2);
-        if (e == hipSuccess) e = hipEventRecord(E[3], ctx->stream);
+            e = launch_A(ctx, ci, MODE_STEP, E(s, ci, 0)[0], E(s, ci, 0)[1]);
+        for (int ci = 0; ci < nc && e == hipSuccess; ++ci)
+            e = launch_cols(ctx, ci, 1, E(s, ci, 1)[0], E(s, ci, 1)[1]);
+        for (int ci = 0; ci < nc && e == hipSuccess; ++ci)
+            if (ctx->classes[ci].dim == 3) e = launch_cols(ctx, ci, 2, E(s, ci, 2)[0], E(s, ci, 2)[1]);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     double acc[3] = {0, 0, 0};
-    for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
-        for (int k = 0; k < 3 && e == hipSuccess; ++k) {
-            float f = 0;
-            e = hipEventElapsedTime(&f, ev[4 * s + k], ev[4 * s + k + 1]);
-            acc[k] += f;
-        }
-    }
+    for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s)
+        for (int ci = 0; ci < nc && e == hipSuccess; ++ci)
+            for (int k = 0; k < ctx->classes[ci].dim && e == hipSuccess; ++k) {
+                float f = 0;
+                e = hipEventElapsedTime(&f, E(s, ci, k)[0], E(s, ci, k)[1]);
+                acc[k] += f;
+            }
     for (auto& x : ev) (void)hipEventDestroy(x);
     if (e != hipSuccess) return fail(ctx, CH_EDEVICE, "kernel timing failed: %s", hipGetErrorString(e));
     ctx->step += nsteps;

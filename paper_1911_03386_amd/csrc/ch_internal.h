@@ -112,9 +112,12 @@ struct ColArgs {
 
 // Kernel launchers (ch_kernels.hip).  prec: 0 = double, 1 = float.  They
 // return hipErrorInvalidValue for an uninstantiated chunk length.
+// ev0/ev1 (optional): events that take the kernel's own start/end timestamps
 hipError_t launch_passA(int prec, int dim, int cx, int rl, int units, const PassAArgs& a,
-                        size_t lds_bytes, hipStream_t s);
-hipError_t launch_col(int prec, int cy, const ColArgs& a, hipStream_t s);
+                        size_t lds_bytes, hipStream_t s, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
+hipError_t launch_col(int prec, int cy, const ColArgs& a, hipStream_t s, hipEvent_t ev0 = nullptr,
+                      hipEvent_t ev1 = nullptr);
 hipError_t launch_init_member(int prec, void* C, int64_t sites, uint64_t seed, double c0,
                               double noise, hipStream_t s);
 hipError_t launch_reset(int64_t* steps, int nsteps, int64_t value, int32_t* flags, int m,

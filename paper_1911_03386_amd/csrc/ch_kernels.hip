@@ -34,6 +34,7 @@
 // element and sweep: four two-term recursions and one scale.
 #include "ch_internal.h"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -444,19 +445,23 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     const int Ract = min(a.R, ny - y0);  // x-lines of this block inside the grid
     const int nrows = Ract + (needG ? 3 : 2);
     const int npl = (DIM == 3) ? (needG ? 4 : 3) : 1;
+    const int nvec = nx / VEC;
+    // Interior: a wavefront stages whole rows (rows of all planes go to the
+    // wavefronts round-robin), its lanes take consecutive 16-byte vectors of a
+    // row in segments of 64, and each lane issues NB loads before it writes
+    // any of them to LDS.  Row bases are wave-uniform (scalar registers).
+    // Halos: one vector on each side of every row, one per thread.
+    const int nwaves = nthreads >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const int nrows_all = npl * nrows;
+    const int nseg = (nvec + 63) >> 6;
     {
-        // Items: per staged row, nx/VEC interior vectors plus one halo vector on
-        // each side.  Each thread issues a batch of loads before writing any of
-        // them to LDS, so the memory latency is paid once per batch.
-        const int nvec = nx / VEC;
-        const int W = nvec + 2;
-        int xi = tid % W, r = tid / W, pl = 0;
-        const int dxi = nthreads % W, drr = nthreads / W;
+        constexpr int NB = 8;
+        int pl = 0, r = wv, seg = 0;  // wave-uniform cursor (plane, row, segment)
         while (r >= nrows) {
             r -= nrows;
             ++pl;
         }
-        constexpr int NB = 8;
         while (pl < npl) {
             VT val[NB];
             int dst[NB];
@@ -466,20 +471,21 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
                 if (pl < npl) {
                     const int zz = (DIM == 3) ? wrapi(z - 1 + pl, nz) : 0;
                     const int yy = wrapi(y0 - 1 + r, ny);
-                    const int xs = xi < nvec ? xi * VEC : (xi == nvec ? nx - HALO : 0);
-                    const int xx = xi < nvec ? xi * VEC + HALO : (xi == nvec ? 0 : nx + HALO);
-                    val[i] = *reinterpret_cast<const VT*>(C + ((int64_t)zz * ny + yy) * nx + xs);
-                    dst[i] = pl * planeStride + r * pitch + xx + (xx / CX) * PADE;
-                }
-                xi += dxi;
-                r += drr;
-                if (xi >= W) {
-                    xi -= W;
-                    ++r;
-                }
-                while (r >= nrows) {
-                    r -= nrows;
-                    ++pl;
+                    const T* row = C + ((int64_t)zz * ny + yy) * nx;
+                    const int xi = seg * 64 + lane;
+                    if (xi < nvec) {
+                        const uint32_t xs = (uint32_t)xi * VEC, xx = xs + HALO;
+                        val[i] = *reinterpret_cast<const VT*>(row + xs);
+                        dst[i] = pl * planeStride + r * pitch + (int)(xx + xx / CX * PADE);
+                    }
+                    if (++seg == nseg) {
+                        seg = 0;
+                        r += nwaves;
+                        while (r >= nrows) {
+                            r -= nrows;
+                            ++pl;
+                        }
+                    }
                 }
             }
 #pragma unroll
@@ -490,6 +496,20 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
 #pragma unroll
                     for (int q = 0; q < VEC; ++q) sC[dst[i] + q] = e[q];
                 }
+        }
+        for (int h = tid; h < 2 * nrows_all; h += nthreads) {
+            const int rid = h >> 1, pl = rid / nrows, r = rid - pl * nrows;
+            const int zz = (DIM == 3) ? wrapi(z - 1 + pl, nz) : 0;
+            const int yy = wrapi(y0 - 1 + r, ny);
+            // left halo: the last vector of the row; right halo: the first
+            const int xs = (h & 1) ? 0 : nx - HALO;
+            const int xx = (h & 1) ? nx + HALO : 0;
+            const VT val = *reinterpret_cast<const VT*>(C + ((int64_t)zz * ny + yy) * nx + xs);
+            T e[VEC];
+            vec_get<T>(val, e);
+            const int d = pl * planeStride + r * pitch + xx + (xx / CX) * PADE;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) sC[d + q] = e[q];
         }
     }
     __syncthreads();
@@ -691,31 +711,33 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
             }
         }
         __syncthreads();
-        const int nvec = nx / VEC;
-        int xv = tid % nvec, rr = tid / nvec;
-        const int dxv = nthreads % nvec, drr = nthreads / nvec;
+        // rows to the wavefronts round-robin, lanes along the row
         constexpr int NB = 8;
+        int rr = wv, seg = 0;  // wave-uniform cursor (row, segment)
         while (rr < Ract) {
             VT val[NB];
-            int64_t gdst[NB];
+            T* row[NB];
+            int off[NB];
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
-                gdst[i] = -1;
+                off[i] = -1;
+                row[i] = Wout + ((int64_t)z * ny + y0 + rr) * nx;
                 if (rr < Ract) {
-                    const int xx = xv * VEC + HALO;
-                    val[i] = vec_make<T>(sC + (rr + 1) * pitch + xx + (xx / CX) * PADE);
-                    gdst[i] = ((int64_t)z * ny + y0 + rr) * nx + xv * VEC;
-                }
-                xv += dxv;
-                rr += drr;
-                if (xv >= nvec) {
-                    xv -= nvec;
-                    ++rr;
+                    const int xv = seg * 64 + lane;
+                    if (xv < nvec) {
+                        const uint32_t xo = (uint32_t)xv * VEC, xx = xo + HALO;
+                        val[i] = vec_make<T>(sC + (rr + 1) * pitch + (int)(xx + xx / CX * PADE));
+                        off[i] = (int)xo;
+                    }
+                    if (++seg == nseg) {
+                        seg = 0;
+                        rr += nwaves;
+                    }
                 }
             }
 #pragma unroll
             for (int i = 0; i < NB; ++i)
-                if (gdst[i] >= 0) *reinterpret_cast<VT*>(Wout + gdst[i]) = val[i];
+                if (off[i] >= 0) *reinterpret_cast<VT*>(row[i] + (uint32_t)off[i]) = val[i];
         }
     }
 
@@ -789,18 +811,19 @@ __global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
     const int pitch = a.pitch;
     const int planeStride = (a.R + 3) * pitch;
     const int nvec = nx / VEC;
-    const int W = nvec + 2;                  // vectors per staged row: interior + 2 halo
+    const int nseg = (nvec + 63) >> 6;     // 64-vector segments of a row
     const int nrows = Ract + (needG ? 3 : 2);
     const int xhi = needG ? 2 : 1;           // highest plane offset the stencils read
+    const int nwaves = nthreads >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
 
-    // vector xi of staged row r of plane zz (the two halo vectors come last)
-    auto load_item = [&](int r, int xi, int zz, VT& val, int& dst) {
-        const int yy = wrapi(y0 - 1 + r, ny);
-        const int zw = wrapi(zz, nz);
-        const int xs = xi < nvec ? xi * VEC : (xi == nvec ? nx - HALO : 0);
-        const int xx = xi < nvec ? xi * VEC + HALO : (xi == nvec ? 0 : nx + HALO);
-        val = *reinterpret_cast<const VT*>(C + ((int64_t)zw * ny + yy) * nx + xs);
-        dst = ((zz - zbase + 1) & 3) * planeStride + r * pitch + xx + (xx / CX) * PADE;
+    // Staging follows the single-plane kernel: a wavefront takes whole rows
+    // (round-robin), its lanes consecutive 16-byte vectors of the row in
+    // segments of 64; halos are one vector per thread.  A plane goes to ring
+    // slot (z - zbase + 1) mod 4.
+    auto slot_of = [&](int zz) { return ((zz - zbase + 1) & 3) * planeStride; };
+    auto row_of = [&](int zz, int r) {
+        return C + ((int64_t)wrapi(zz, nz) * ny + wrapi(y0 - 1 + r, ny)) * nx;
     };
     auto put = [&](const VT& val, int dst) {
         T e[VEC];
@@ -808,35 +831,51 @@ __global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
 #pragma unroll
         for (int q = 0; q < VEC; ++q) sC[dst + q] = e[q];
     };
-
-    // Items (row, vector) of a plane are dealt to the threads round-robin:
-    // thread t takes items t, t + nthreads, ...; a cursor (r, xi) steps
-    // through them without divisions.
-    const int dxi = nthreads % W, dr = nthreads / W;
-    const int r_first = tid / W, xi_first = tid - r_first * W;
-    auto step_item = [&](int& r, int& xi) {
-        xi += dxi;
-        r += dr;
-        if (xi >= W) {
-            xi -= W;
-            ++r;
+    // interior vector seg*64+lane of row r of plane zz (if the lane has one)
+    auto load_vec = [&](int zz, int r, int seg, VT& val, int& dst) {
+        const int xi = seg * 64 + lane;
+        if (xi < nvec) {
+            const uint32_t xs = (uint32_t)xi * VEC, xx = xs + HALO;
+            val = *reinterpret_cast<const VT*>(row_of(zz, r) + xs);
+            dst = slot_of(zz) + r * pitch + (int)(xx + xx / CX * PADE);
         }
     };
+    // halo vector h (row h / 2; left side for even h) of plane zz
+    auto load_halo = [&](int zz, int h, VT& val, int& dst) {
+        const int r = h >> 1;
+        const int xs = (h & 1) ? 0 : nx - HALO;
+        const int xx = (h & 1) ? nx + HALO : 0;
+        val = *reinterpret_cast<const VT*>(row_of(zz, r) + xs);
+        dst = slot_of(zz) + r * pitch + xx + (xx / CX) * PADE;
+    };
+
     // first unit: planes zbase-1 .. zbase+xhi, in batches of NPF loads
     for (int p = 0; p < xhi + 2; ++p) {
-        int r = r_first, xi = xi_first;
+        const int zz = zbase - 1 + p;
+        int r = wv, seg = 0;  // wave-uniform cursor (row, segment)
         while (r < nrows) {
             VT pv[NPF];
             int pd[NPF];
 #pragma unroll
             for (int i = 0; i < NPF; ++i) {
                 pd[i] = -1;
-                if (r < nrows) load_item(r, xi, zbase - 1 + p, pv[i], pd[i]);
-                step_item(r, xi);
+                if (r < nrows) {
+                    load_vec(zz, r, seg, pv[i], pd[i]);
+                    if (++seg == nseg) {
+                        seg = 0;
+                        r += nwaves;
+                    }
+                }
             }
 #pragma unroll
             for (int i = 0; i < NPF; ++i)
                 if (pd[i] >= 0) put(pv[i], pd[i]);
+        }
+        for (int h = tid; h < 2 * nrows; h += nthreads) {
+            VT v;
+            int d;
+            load_halo(zz, h, v, d);
+            put(v, d);
         }
     }
     __syncthreads();
@@ -863,17 +902,25 @@ __global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
         const int z = zbase + u;
         const bool has_next = u + 1 < nunits;
         // rows of the plane the next unit adds start loading now (the host
-        // guarantees one plane fits NPF vectors per thread)
-        VT pv[NPF];
-        int pd[NPF];
+        // guarantees that a wavefront's share of one plane fits NPF vectors
+        // per lane and the halos one vector per thread)
+        VT pv[NPF], ph;
+        int pd[NPF], phd = -1;
         {
-            int r = r_first, xi = xi_first;
+            const int zz = z + 1 + xhi;
+            int r = wv, seg = 0;  // wave-uniform cursor (row, segment)
 #pragma unroll
             for (int i = 0; i < NPF; ++i) {
                 pd[i] = -1;
-                if (has_next && r < nrows) load_item(r, xi, z + 1 + xhi, pv[i], pd[i]);
-                step_item(r, xi);
+                if (has_next && r < nrows) {
+                    load_vec(zz, r, seg, pv[i], pd[i]);
+                    if (++seg == nseg) {
+                        seg = 0;
+                        r += nwaves;
+                    }
+                }
             }
+            if (has_next && tid < 2 * nrows) load_halo(zz, tid, ph, phd);
         }
 
         // ring slots of planes z-1 .. z+2
@@ -1028,6 +1075,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
 #pragma unroll
             for (int i = 0; i < NPF; ++i)
                 if (pd[i] >= 0) put(pv[i], pd[i]);
+            if (phd >= 0) put(ph, phd);
             __syncthreads();
         }
     }
@@ -1252,8 +1300,22 @@ __global__ void beta_kernel(const double* series, int64_t max_samples, int32_t m
 // --------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------
+// With a pair of events, the events take the kernel's own start and end
+// timestamps (hipExtLaunchKernel), so no extra packets sit between kernels.
+template <typename K, typename A>
+static hipError_t launch_k(K k, unsigned blocks, unsigned threads, size_t lds, hipStream_t s,
+                           const A& a, hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (ev0 && ev1)
+        hipExtLaunchKernelGGL(k, dim3(blocks), dim3(threads), (std::uint32_t)lds, s, ev0, ev1, 0, a);
+    else
+        hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
 template <typename T, int DIM, int CX, int RL>
-static hipError_t launchA(const PassAArgs& a, size_t lds, hipStream_t s)
+static hipError_t launchA(const PassAArgs& a, size_t lds, hipStream_t s, hipEvent_t ev0,
+                          hipEvent_t ev1)
 {
     auto k = passA_kernel<T, DIM, CX, RL>;
     if (lds > 65536) {
@@ -1261,12 +1323,12 @@ static hipError_t launchA(const PassAArgs& a, size_t lds, hipStream_t s)
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k, dim3((unsigned)a.nblocks), dim3(64 * a.waves), lds, s, a);
-    return hipGetLastError();
+    return launch_k(k, (unsigned)a.nblocks, 64 * a.waves, lds, s, a, ev0, ev1);
 }
 
 template <typename T, int CX, int RL>
-static hipError_t launchRing(const PassAArgs& a, size_t lds, hipStream_t s)
+static hipError_t launchRing(const PassAArgs& a, size_t lds, hipStream_t s, hipEvent_t ev0,
+                             hipEvent_t ev1)
 {
     auto k = passA_ring_kernel<T, CX, RL>;
     if (lds > 65536) {
@@ -1274,8 +1336,7 @@ static hipError_t launchRing(const PassAArgs& a, size_t lds, hipStream_t s)
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k, dim3((unsigned)a.nblocks), dim3(64 * a.waves), lds, s, a);
-    return hipGetLastError();
+    return launch_k(k, (unsigned)a.nblocks, 64 * a.waves, lds, s, a, ev0, ev1);
 }
 
 // (chunk length, lines per lane) pairs that are compiled
@@ -1286,18 +1347,18 @@ static hipError_t launchRing(const PassAArgs& a, size_t lds, hipStream_t s)
 
 template <typename T, int DIM>
 static hipError_t launchA_shape(int cx, int rl, int units, const PassAArgs& a, size_t lds,
-                                hipStream_t s)
+                                hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (DIM == 3 && units > 1) {
 #define X(C, R) \
-    if (cx == C && rl == R) return launchRing<T, C, R>(a, lds, s);
+    if (cx == C && rl == R) return launchRing<T, C, R>(a, lds, s, ev0, ev1);
         CH_RING_SHAPES(X)
 #undef X
         return hipErrorInvalidValue;
     }
     if (units != 1) return hipErrorInvalidValue;
 #define X(C, R) \
-    if (cx == C && rl == R) return launchA<T, DIM, C, R>(a, lds, s);
+    if (cx == C && rl == R) return launchA<T, DIM, C, R>(a, lds, s, ev0, ev1);
     CH_PASSA_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
@@ -1326,36 +1387,35 @@ int passA_pad(int prec) { return prec == 0 ? PadOf<double>::v : PadOf<float>::v;
 int passA_halo(int prec) { return prec == 0 ? Vec16<double>::n : Vec16<float>::n; }
 
 hipError_t launch_passA(int prec, int dim, int cx, int rl, int units, const PassAArgs& a,
-                        size_t lds, hipStream_t s)
+                        size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (a.nblocks <= 0) return hipSuccess;
     if (prec == 0)
-        return dim == 2 ? launchA_shape<double, 2>(cx, rl, units, a, lds, s)
-                        : launchA_shape<double, 3>(cx, rl, units, a, lds, s);
-    return dim == 2 ? launchA_shape<float, 2>(cx, rl, units, a, lds, s)
-                    : launchA_shape<float, 3>(cx, rl, units, a, lds, s);
+        return dim == 2 ? launchA_shape<double, 2>(cx, rl, units, a, lds, s, ev0, ev1)
+                        : launchA_shape<double, 3>(cx, rl, units, a, lds, s, ev0, ev1);
+    return dim == 2 ? launchA_shape<float, 2>(cx, rl, units, a, lds, s, ev0, ev1)
+                    : launchA_shape<float, 3>(cx, rl, units, a, lds, s, ev0, ev1);
 }
 
 template <typename T, int CY>
-static hipError_t launchC(const ColArgs& a, hipStream_t s)
+static hipError_t launchC(const ColArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     const size_t lds = ((size_t)5 * a.b * a.P + a.b) * sizeof(T);
     const int threads = (a.b * a.P + 63) / 64 * 64;
-    hipLaunchKernelGGL((col_kernel<T, CY>), dim3((unsigned)a.nblocks), dim3(threads), lds, s, a);
-    return hipGetLastError();
+    return launch_k(col_kernel<T, CY>, (unsigned)a.nblocks, threads, lds, s, a, ev0, ev1);
 }
 
 template <typename T>
-static hipError_t launchC_cy(int cy, const ColArgs& a, hipStream_t s)
+static hipError_t launchC_cy(int cy, const ColArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     switch (cy) {
-    case 4: return launchC<T, 4>(a, s);
-    case 8: return launchC<T, 8>(a, s);
-    case 16: return launchC<T, 16>(a, s);
-    case 32: return launchC<T, 32>(a, s);
+    case 4: return launchC<T, 4>(a, s, ev0, ev1);
+    case 8: return launchC<T, 8>(a, s, ev0, ev1);
+    case 16: return launchC<T, 16>(a, s, ev0, ev1);
+    case 32: return launchC<T, 32>(a, s, ev0, ev1);
     case 64:
         // 64 doubles per lane exceed the register file: FP32 only
-        if constexpr (sizeof(T) == 4) return launchC<T, 64>(a, s);
+        if constexpr (sizeof(T) == 4) return launchC<T, 64>(a, s, ev0, ev1);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
@@ -1367,11 +1427,12 @@ bool col_has(int prec, int cy)
     return cy == 4 || cy == 8 || cy == 16 || cy == 32 || cy == 64;
 }
 
-hipError_t launch_col(int prec, int cy, const ColArgs& a, hipStream_t s)
+hipError_t launch_col(int prec, int cy, const ColArgs& a, hipStream_t s, hipEvent_t ev0,
+                      hipEvent_t ev1)
 {
     if (a.nblocks <= 0) return hipSuccess;
     if (!col_has(prec, cy)) return hipErrorInvalidValue;
-    return prec == 0 ? launchC_cy<double>(cy, a, s) : launchC_cy<float>(cy, a, s);
+    return prec == 0 ? launchC_cy<double>(cy, a, s, ev0, ev1) : launchC_cy<float>(cy, a, s, ev0, ev1);
 }
 
 hipError_t launch_init_member(int prec, void* C, int64_t sites, uint64_t seed, double c0,
