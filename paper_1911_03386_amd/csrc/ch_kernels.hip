@@ -400,6 +400,40 @@ struct PadOf<float> {
 // --------------------------------------------------------------------------
 // pass A: RHS + diagnostics + x-line solves
 // --------------------------------------------------------------------------
+// RHS of the scheme at line q, element m of a lane's staged rows:
+//   C + dt lap_h(C^3 - C) - 2 gamma dt sum_{d<e} D_d D_e C
+// `at(dz, dy, m)` reads the staged field.  A mixed term D_d D_e C is formed
+// as the d-second difference of e-second differences; the inner differences
+// and the values of C^3 - C at neighbouring sites are the same expressions a
+// neighbouring element or line of the lane forms, so the unrolled loops
+// compute each of them once.
+template <typename T, int DIM, typename At>
+__device__ __forceinline__ T rhs_site(const At& at, int q, int m, T ihx2, T ihy2, T ihz2, T dt, T tg,
+                                      T cxy, T cxz, T cyz)
+{
+    auto N = [](T c) { return c * c * c - c; };
+    auto dyy = [&](int dz, int mm) {
+        return at(dz, q + 1, mm) + at(dz, q - 1, mm) - T(2) * at(dz, q, mm);
+    };
+    const T c = at(0, q, m);
+    const T Nc = N(c);
+    T lapN = (N(at(0, q, m + 1)) + N(at(0, q, m - 1)) - T(2) * Nc) * ihx2 +
+             (N(at(0, q + 1, m)) + N(at(0, q - 1, m)) - T(2) * Nc) * ihy2;
+    const T dy0 = dyy(0, m);
+    T cross = (dyy(0, m + 1) + dyy(0, m - 1) - T(2) * dy0) * cxy;
+    if (DIM == 3) {
+        auto dzz = [&](int dy, int mm) {
+            return at(1, q + dy, mm) + at(-1, q + dy, mm) - T(2) * at(0, q + dy, mm);
+        };
+        lapN += (N(at(1, q, m)) + N(at(-1, q, m)) - T(2) * Nc) * ihz2;
+        const T dz0 = dzz(0, m);
+        cross += (dzz(0, m + 1) + dzz(0, m - 1) - T(2) * dz0) * cxz;
+        cross += (dzz(1, m) + dzz(-1, m) - T(2) * dz0) * cyz;
+    }
+    return c + dt * lapN - tg * cross;
+}
+
+
 template <typename T, int DIM, int CX, int RL>
 __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
 {
@@ -537,49 +571,21 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     const T cxy = (T)(md.ih2[0] * md.ih2[1]);
     const T cxz = (T)(md.ih2[0] * md.ih2[2]), cyz = (T)(md.ih2[1] * md.ih2[2]);
 
+    // The RHS is formed on every lane: lines past the end of a ragged last
+    // band read staged rows that exist (R + 3 are allocated) and their
+    // results are never stored or summed.
     T v[RL][CX];
+    if (solve) {
+        auto at = [&](int dz, int dy, int m) { return AT(dz, dy, m); };
 #pragma unroll
-    for (int q = 0; q < RL; ++q)
+        for (int k = 0; k < CX; ++k)
 #pragma unroll
-        for (int k = 0; k < CX; ++k) v[q][k] = T(0);
+            for (int q = 0; q < RL; ++q)
+                v[q][k] = rhs_site<T, DIM>(at, q, k + HALO, ihx2, ihy2, ihz2, dt, tg, cxy, cxz, cyz);
+    }
 
     double pF = 0.0, pS = 0.0, pG = 0.0;
     if (active) {
-        if (solve) {
-#pragma unroll
-            for (int k = 0; k < CX; ++k) {
-                const int m0 = k + HALO;
-                // N = C^3 - C and the x second difference of C on lines -1 .. RL
-                T Nr[RL + 2], Dx[RL + 2];
-#pragma unroll
-                for (int q = 0; q < RL + 2; ++q) {
-                    const T c = AT(0, q - 1, m0);
-                    Nr[q] = c * c * c - c;
-                    Dx[q] = AT(0, q - 1, m0 + 1) - T(2) * c + AT(0, q - 1, m0 - 1);
-                }
-#pragma unroll
-                for (int q = 0; q < RL; ++q) {
-                    const T c = AT(0, q, m0), cw = AT(0, q, m0 - 1), ce = AT(0, q, m0 + 1);
-                    const T Nw = cw * cw * cw - cw, Ne = ce * ce * ce - ce;
-                    const T Nc = Nr[q + 1];
-                    T lapN = (Ne - T(2) * Nc + Nw) * ihx2 + (Nr[q + 2] - T(2) * Nc + Nr[q]) * ihy2;
-                    T cross = (Dx[q + 2] - T(2) * Dx[q + 1] + Dx[q]) * cxy;
-                    if (DIM == 3) {
-                        const T cu = AT(1, q, m0), cd = AT(-1, q, m0);
-                        const T Nu = cu * cu * cu - cu, Nd = cd * cd * cd - cd;
-                        lapN += (Nu - T(2) * Nc + Nd) * ihz2;
-                        const T dxxu = AT(1, q, m0 + 1) - T(2) * cu + AT(1, q, m0 - 1);
-                        const T dxxd = AT(-1, q, m0 + 1) - T(2) * cd + AT(-1, q, m0 - 1);
-                        cross += (dxxu - T(2) * Dx[q + 1] + dxxd) * cxz;
-                        const T dyy0 = AT(0, q + 1, m0) - T(2) * c + AT(0, q - 1, m0);
-                        const T dyyu = AT(1, q + 1, m0) - T(2) * cu + AT(1, q - 1, m0);
-                        const T dyyd = AT(-1, q + 1, m0) - T(2) * cd + AT(-1, q - 1, m0);
-                        cross += (dyyu - T(2) * dyy0 + dyyd) * cyz;
-                    }
-                    v[q][k] = c + dt * lapN - tg * cross;
-                }
-            }
-        }
         if (needF) {
             const double cbulk = a.conv ? 0.5 : 0.25;
             const double hg = 0.5 * md.gamma;
@@ -931,45 +937,17 @@ __global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
 #define AT(dz, dy, m) \
     sC[((dz) < 0 ? s0 : (dz) == 0 ? s1 : (dz) == 1 ? s2 : s3) + (dy) * pitch + (m) + ((m) / CX) * PADE]
 
+        // every lane forms the RHS (see the single-plane kernel)
         T v[RL][CX];
+        if (solve) {
+            auto at = [&](int dz, int dy, int m) { return AT(dz, dy, m); };
 #pragma unroll
-        for (int q = 0; q < RL; ++q)
+            for (int k = 0; k < CX; ++k)
 #pragma unroll
-            for (int k = 0; k < CX; ++k) v[q][k] = T(0);
-
+                for (int q = 0; q < RL; ++q)
+                    v[q][k] = rhs_site<T, 3>(at, q, k + HALO, ihx2, ihy2, ihz2, dt, tg, cxy, cxz, cyz);
+        }
         if (active) {
-            if (solve) {
-#pragma unroll
-                for (int k = 0; k < CX; ++k) {
-                    const int m0 = k + HALO;
-                    T Nr[RL + 2], Dx[RL + 2];
-#pragma unroll
-                    for (int q = 0; q < RL + 2; ++q) {
-                        const T c = AT(0, q - 1, m0);
-                        Nr[q] = c * c * c - c;
-                        Dx[q] = AT(0, q - 1, m0 + 1) - T(2) * c + AT(0, q - 1, m0 - 1);
-                    }
-#pragma unroll
-                    for (int q = 0; q < RL; ++q) {
-                        const T c = AT(0, q, m0), cw = AT(0, q, m0 - 1), ce = AT(0, q, m0 + 1);
-                        const T Nw = cw * cw * cw - cw, Ne = ce * ce * ce - ce;
-                        const T Nc = Nr[q + 1];
-                        T lapN = (Ne - T(2) * Nc + Nw) * ihx2 + (Nr[q + 2] - T(2) * Nc + Nr[q]) * ihy2;
-                        T cross = (Dx[q + 2] - T(2) * Dx[q + 1] + Dx[q]) * cxy;
-                        const T cu = AT(1, q, m0), cd = AT(-1, q, m0);
-                        const T Nu = cu * cu * cu - cu, Nd = cd * cd * cd - cd;
-                        lapN += (Nu - T(2) * Nc + Nd) * ihz2;
-                        const T dxxu = AT(1, q, m0 + 1) - T(2) * cu + AT(1, q, m0 - 1);
-                        const T dxxd = AT(-1, q, m0 + 1) - T(2) * cd + AT(-1, q, m0 - 1);
-                        cross += (dxxu - T(2) * Dx[q + 1] + dxxd) * cxz;
-                        const T dyy0 = AT(0, q + 1, m0) - T(2) * c + AT(0, q - 1, m0);
-                        const T dyyu = AT(1, q + 1, m0) - T(2) * cu + AT(1, q - 1, m0);
-                        const T dyyd = AT(-1, q + 1, m0) - T(2) * cd + AT(-1, q - 1, m0);
-                        cross += (dyyu - T(2) * dyy0 + dyyd) * cyz;
-                        v[q][k] = c + dt * lapN - tg * cross;
-                    }
-                }
-            }
             if (needF) {
                 const double cbulk = a.conv ? 0.5 : 0.25;
                 const double hg = 0.5 * md.gamma;
