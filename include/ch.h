@@ -158,8 +158,10 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path);
 /* Number of size classes (members grouped by dimension and grid shape, in
  * order of first appearance) and explicit tile shapes for one class.  The
  * RHS + x-solve pass: cx = elements per lane of an x-line, rl = x-lines per
- * lane, waves = wavefronts per block, units = z-planes of one y-band a 3D
- * block walks through with a ring of staged planes (1 in 2D).  The y-solve: cy = elements per
+ * lane, waves = wavefronts per block, units = work units a block walks
+ * through, loading the next one while it computes the current one (y-bands
+ * in 2D; z-planes of one y-band in 3D, with a ring of staged planes).  The
+ * y-solve: cy = elements per
  * lane, by = columns per block; cz/bz the same for the z-solve (ignored in
  * 2D).  CH_EUNSUPPORTED if the shape is not valid for the class (nothing
  * changes then). */

@@ -100,7 +100,10 @@ bool planA(ClassPlan& c, int prec, int cx, int rl, int waves, int units)
     c.bands = (c.ny + R - 1) / R;
     c.pitch = pitch;
     c.ldsA = lds;
-    c.bpmA = (int64_t)c.bands * ((c.nz + units - 1) / units);
+    if (c.dim == 2)
+        c.bpmA = (c.bands + units - 1) / units;
+    else
+        c.bpmA = (int64_t)c.bands * ((c.nz + units - 1) / units);
     c.nblocksA = (int64_t)c.members.size() * c.bpmA;
     return true;
 }
@@ -1056,10 +1059,10 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
         // pass A candidates (timing mode: reads C, writes the scratch field)
         float best = 1e30f;
         int bcx = c.cx, brl = c.rl, bw = c.waves, bu = c.units;
-        const int unit_opts_2d[] = {1};
+        const int unit_opts_2d[] = {1, 2, 4};
         const int unit_opts_3d[] = {1, 4, 8, 16, 32};
         const int* uo = c.dim == 3 ? unit_opts_3d : unit_opts_2d;
-        const int nuo = c.dim == 3 ? 5 : 1;
+        const int nuo = c.dim == 3 ? 5 : 3;
         for (int waves : {4, 2, 1})
             for (int rl : {1, 2, 4})
                 for (int cx : {4, 8, 16, 32, 64})

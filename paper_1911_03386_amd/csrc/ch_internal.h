@@ -12,7 +12,7 @@ constexpr int kWaveScanLevels = 6; // lanes of one line inside a wavefront: P <=
 constexpr int kSeriesSlots = 5;    // F(jK-1), F(jK), F(jK+1), <C>(jK), G_id(jK)
 constexpr int kPassAThreads = 256; // 4 wavefronts
 constexpr int kColMaxThreads = 512;
-constexpr int kPrefetchVecs = 12;  // 3D plane ring: 16-byte vectors per thread prefetched for the next plane
+constexpr int kPrefetchVecs = 12;  // several-unit pass A: 16-byte vectors per lane prefetched for the next unit
 
 // Coefficients of the periodic solve (I + rho [1,-4,6,-4,1]) y = x along one
 // axis of one member, factored as y = ikappa * Qa^{-1} Qc^{-1} x with the
@@ -81,7 +81,7 @@ struct PassAArgs {
     int32_t waves;             // wavefronts per block (1, 2 or 4)
     int32_t R;                 // x-lines per block (= waves * rows_per_wave)
     int32_t bands_y;           // y-bands per (member, z) = ceil(ny / R)
-    int32_t units;             // work units per block: y-bands (2D) or z-planes (3D)
+    int32_t units;             // work units per block: y-bands (2D) or z-planes of a y-band (3D)
     int64_t blocks_per_member;
     int64_t nblocks;           // blocks of this launch
     int32_t pitch;             // LDS row pitch (elements)
@@ -126,7 +126,7 @@ hipError_t launch_fin(const FinArgs& f, hipStream_t s);
 hipError_t launch_beta(const double* series, int64_t max_samples, int32_t member, int32_t K,
                        int64_t ncur, double dt, double* out, int64_t J, hipStream_t s);
 
-bool passA_has(int dim, int cx, int rl, int units);  // units > 1: 3D plane ring
+bool passA_has(int dim, int cx, int rl, int units);  // units > 1: several units per block
 bool col_has(int prec, int cy);
 int passA_pad(int prec);       // LDS padding (elements) after every chunk
 int passA_halo(int prec);      // periodic halo columns on each side of an LDS row

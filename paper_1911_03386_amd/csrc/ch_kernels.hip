@@ -17,8 +17,10 @@
 //                 of F, sum C and the dF/dt identity; the first blocks of the
 //                 step's last line sweep reduce them per member in a fixed
 //                 order.
-//   passA_ring_kernel  the same for 3D, one block walking several z-planes of
-//                 a y-band through a ring of staged planes.
+//   passA_multi_kernel  the same with one block walking several work units
+//                 (y-bands in 2D, z-planes of a y-band through a ring of
+//                 staged planes in 3D), the next unit's rows loading while
+//                 the current one is computed.
 //   col_kernel    y- or z-lines.  A block owns b adjacent columns; lane
 //                 (column, chunk) holds a contiguous chunk of one line in
 //                 registers, loads are coalesced across columns.
@@ -400,6 +402,67 @@ struct PadOf<float> {
 // --------------------------------------------------------------------------
 // pass A: RHS + diagnostics + x-line solves
 // --------------------------------------------------------------------------
+// A lane's results (lines rl0 .. rl0+RL-1, chunk j) go to LDS rows of `so`
+// in the staging layout, and each wavefront then stores the lines it holds
+// itself (lines wv*rpw .. wv*rpw+rpw-1 of the unit) with coalesced 16-byte
+// stores, lanes along the line.  The rows a wavefront reads back are the rows
+// it wrote, and a wavefront's LDS operations complete in order, so only a
+// wavefront-scope fence sits between the two.  The caller ends every read of
+// these LDS rows (a block barrier) first.
+template <typename T, int CX, int RL>
+__device__ __forceinline__ void write_back(T* so, int pitch, const T (&v)[RL][CX], const bool (&rowok)[RL],
+                                           int rl0, int j, int wv, int lane, int rpw, int Ract, int nvec,
+                                           T* out, int nx)
+{
+    constexpr int PADE = PadOf<T>::v;
+    constexpr int VEC = Vec16<T>::n;
+    constexpr int HALO = VEC;
+    using VT = typename Vec16<T>::type;
+#pragma unroll
+    for (int q = 0; q < RL; ++q) {
+        if (!rowok[q]) continue;
+        T* sr = so + (rl0 + q) * pitch + j * (CX + PADE);
+#pragma unroll
+        for (int k = 0; k < CX; ++k) {
+            const int m = k + HALO;
+            sr[m + (m / CX) * PADE] = v[q][k];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int nseg = (nvec + 63) >> 6;
+    const int l1 = min(wv * rpw + rpw, Ract);
+    constexpr int NB = 8;
+    int l = wv * rpw, seg = 0;  // wave-uniform cursor (line, segment)
+    while (l < l1) {
+        VT val[NB];
+        T* row[NB];
+        int off[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            off[i] = -1;
+            row[i] = out + (int64_t)l * nx;
+            if (l < l1) {
+                const int xv = seg * 64 + lane;
+                if (xv < nvec) {
+                    const uint32_t xo = (uint32_t)xv * VEC, xx = xo + HALO;
+                    val[i] = vec_make<T>(so + l * pitch + (int)(xx + xx / CX * PADE));
+                    off[i] = (int)xo;
+                }
+                if (++seg == nseg) {
+                    seg = 0;
+                    ++l;
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            if (off[i] >= 0) *reinterpret_cast<VT*>(row[i] + (uint32_t)off[i]) = val[i];
+    }
+}
+
+
 // RHS of the scheme at line q, element m of a lane's staged rows:
 //   C + dt lap_h(C^3 - C) - 2 gamma dt sum_{d<e} D_d D_e C
 // `at(dz, dy, m)` reads the staged field.  A mixed term D_d D_e C is formed
@@ -705,47 +768,10 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     __syncthreads();  // LDS stencil reads done; wave partials visible
 
     // ---- write w through LDS (coalesced) -------------------------------------
-    if (solve) {
-#pragma unroll
-        for (int q = 0; q < RL; ++q) {
-            if (!rowok[q]) continue;
-            T* so = sC + (rl0 + q + 1) * pitch + j * (CX + PADE);  // plane slot 0 is free now
-#pragma unroll
-            for (int k = 0; k < CX; ++k) {
-                const int m = k + HALO;
-                so[m + (m / CX) * PADE] = v[q][k];
-            }
-        }
-        __syncthreads();
-        // rows to the wavefronts round-robin, lanes along the row
-        constexpr int NB = 8;
-        int rr = wv, seg = 0;  // wave-uniform cursor (row, segment)
-        while (rr < Ract) {
-            VT val[NB];
-            T* row[NB];
-            int off[NB];
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                off[i] = -1;
-                row[i] = Wout + ((int64_t)z * ny + y0 + rr) * nx;
-                if (rr < Ract) {
-                    const int xv = seg * 64 + lane;
-                    if (xv < nvec) {
-                        const uint32_t xo = (uint32_t)xv * VEC, xx = xo + HALO;
-                        val[i] = vec_make<T>(sC + (rr + 1) * pitch + (int)(xx + xx / CX * PADE));
-                        off[i] = (int)xo;
-                    }
-                    if (++seg == nseg) {
-                        seg = 0;
-                        rr += nwaves;
-                    }
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < NB; ++i)
-                if (off[i] >= 0) *reinterpret_cast<VT*>(row[i] + (uint32_t)off[i]) = val[i];
-        }
-    }
+    // (the __syncthreads above ended every read of the staged rows)
+    if (solve)
+        write_back<T, CX, RL>(sC + pitch, pitch, v, rowok, rl0, j, wv, lane, a.rows_per_wave, Ract, nvec,
+                              Wout + ((int64_t)z * ny + y0) * nx, nx);
 
     // ---- block partials of F, sum C, sum |grad mu|^2 (reduced by finalize) ----
     if (blk == 0 && tid == 0 && a.mode != MODE_TIMING) *a.nstamp = n;
@@ -763,17 +789,20 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
 }
 
 // --------------------------------------------------------------------------
-// pass A, 3D, several z-planes per block
+// pass A, several work units per block
 // --------------------------------------------------------------------------
-// A block owns a y-band of R x-lines and walks `units` consecutive z-planes
-// of it.  LDS holds a ring of 4 staged planes, so every plane of the band is
-// read from memory once per block instead of three or four times.  While one
-// plane is computed, the rows of the plane the next one adds are loaded into
-// registers; they go to LDS once every read of the ring slot they replace is
-// done.  Results are stored from registers: each lane writes its contiguous
-// chunk, so the ring needs no output buffer.
-template <typename T, int CX, int RL>
-__global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
+// A block walks `units` work units and loads the next unit's rows into
+// registers while it computes the current one; they go to LDS once every read
+// of the rows they replace is done.
+//   2D: a unit is a y-band of R x-lines; the block takes consecutive bands of
+//       one member.  Results leave through LDS with coalesced stores.
+//   3D: a unit is one z-plane of a y-band; the block takes consecutive planes
+//       of one band.  LDS holds a ring of 4 staged planes, so every plane is
+//       read from memory once per block instead of three or four times, and a
+//       unit adds one plane.  Results are stored from registers (each lane
+//       writes its contiguous chunk), so the ring needs no output space.
+template <typename T, int DIM, int CX, int RL>
+__global__ void __launch_bounds__(kPassAThreads) passA_multi_kernel(PassAArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* sC = reinterpret_cast<T*>(lds_raw);
@@ -793,11 +822,10 @@ __global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
     const int64_t bpm = a.blocks_per_member;
     const int mloc = (int)(blk / bpm);
     const int64_t rem = blk - (int64_t)mloc * bpm;
-    const int band = (int)(rem % a.bands_y);
-    const int zbase = (int)(rem / a.bands_y) * a.units;
-    const int nunits = min(a.units, nz - zbase);
-    const int y0 = band * a.R;
-    const int Ract = min(a.R, ny - y0);
+    // 2D: bands band0 .. band0 + nunits - 1;  3D: planes zbase .. zbase + nunits - 1 of band0
+    const int band0 = (DIM == 2) ? (int)rem * a.units : (int)(rem % a.bands_y);
+    const int zbase = (DIM == 2) ? 0 : (int)(rem / a.bands_y) * a.units;
+    const int nunits = (DIM == 2) ? min(a.units, a.bands_y - band0) : min(a.units, nz - zbase);
     const int mid = a.mids[mloc];
     const MemberDev& md = a.mem[mid];
     const T* C = reinterpret_cast<const T*>(a.C) + md.off;
@@ -818,18 +846,22 @@ __global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
     const int planeStride = (a.R + 3) * pitch;
     const int nvec = nx / VEC;
     const int nseg = (nvec + 63) >> 6;     // 64-vector segments of a row
-    const int nrows = Ract + (needG ? 3 : 2);
     const int xhi = needG ? 2 : 1;           // highest plane offset the stencils read
     const int nwaves = nthreads >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
 
-    // Staging follows the single-plane kernel: a wavefront takes whole rows
+    // lines of unit u: y0 .. y0 + Ract - 1, staged rows y0 - 1 .. y0 - 1 + nrows - 1
+    auto unit_y0 = [&](int u) { return (DIM == 2 ? band0 + u : band0) * a.R; };
+    auto unit_rows = [&](int u) { return min(a.R, ny - unit_y0(u)) + (needG ? 3 : 2); };
+
+    // Staging follows the single-unit kernel: a wavefront takes whole rows
     // (round-robin), its lanes consecutive 16-byte vectors of the row in
-    // segments of 64; halos are one vector per thread.  A plane goes to ring
-    // slot (z - zbase + 1) mod 4.
-    auto slot_of = [&](int zz) { return ((zz - zbase + 1) & 3) * planeStride; };
-    auto row_of = [&](int zz, int r) {
-        return C + ((int64_t)wrapi(zz, nz) * ny + wrapi(y0 - 1 + r, ny)) * nx;
+    // segments of 64; halos are one vector per thread.  In 3D a plane goes
+    // to ring slot (z - zbase + 1) mod 4.
+    auto slot_of = [&](int zz) { return (DIM == 3) ? ((zz - zbase + 1) & 3) * planeStride : 0; };
+    auto row_of = [&](int zz, int yfirst, int r) {
+        const int zw = (DIM == 3) ? wrapi(zz, nz) : 0;
+        return C + ((int64_t)zw * ny + wrapi(yfirst - 1 + r, ny)) * nx;
     };
     auto put = [&](const VT& val, int dst) {
         T e[VEC];
@@ -837,51 +869,56 @@ __global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
 #pragma unroll
         for (int q = 0; q < VEC; ++q) sC[dst + q] = e[q];
     };
-    // interior vector seg*64+lane of row r of plane zz (if the lane has one)
-    auto load_vec = [&](int zz, int r, int seg, VT& val, int& dst) {
+    // interior vector seg*64+lane of staged row r (plane zz, first line
+    // yfirst), if the lane has one
+    auto load_vec = [&](int zz, int yfirst, int r, int seg, VT& val, int& dst) {
         const int xi = seg * 64 + lane;
         if (xi < nvec) {
             const uint32_t xs = (uint32_t)xi * VEC, xx = xs + HALO;
-            val = *reinterpret_cast<const VT*>(row_of(zz, r) + xs);
+            val = *reinterpret_cast<const VT*>(row_of(zz, yfirst, r) + xs);
             dst = slot_of(zz) + r * pitch + (int)(xx + xx / CX * PADE);
         }
     };
-    // halo vector h (row h / 2; left side for even h) of plane zz
-    auto load_halo = [&](int zz, int h, VT& val, int& dst) {
+    // halo vector h (row h / 2; left side for even h)
+    auto load_halo = [&](int zz, int yfirst, int h, VT& val, int& dst) {
         const int r = h >> 1;
         const int xs = (h & 1) ? 0 : nx - HALO;
         const int xx = (h & 1) ? nx + HALO : 0;
-        val = *reinterpret_cast<const VT*>(row_of(zz, r) + xs);
+        val = *reinterpret_cast<const VT*>(row_of(zz, yfirst, r) + xs);
         dst = slot_of(zz) + r * pitch + xx + (xx / CX) * PADE;
     };
 
-    // first unit: planes zbase-1 .. zbase+xhi, in batches of NPF loads
-    for (int p = 0; p < xhi + 2; ++p) {
-        const int zz = zbase - 1 + p;
-        int r = wv, seg = 0;  // wave-uniform cursor (row, segment)
-        while (r < nrows) {
-            VT pv[NPF];
-            int pd[NPF];
+    // first unit: its rows (2D) or planes zbase-1 .. zbase+xhi (3D), in
+    // batches of NPF loads
+    {
+        const int yf = unit_y0(0), nrows = unit_rows(0);
+        for (int p = 0; p < (DIM == 3 ? xhi + 2 : 1); ++p) {
+            const int zz = zbase - 1 + p;
+            int r = wv, seg = 0;  // wave-uniform cursor (row, segment)
+            while (r < nrows) {
+                VT pv[NPF];
+                int pd[NPF];
 #pragma unroll
-            for (int i = 0; i < NPF; ++i) {
-                pd[i] = -1;
-                if (r < nrows) {
-                    load_vec(zz, r, seg, pv[i], pd[i]);
-                    if (++seg == nseg) {
-                        seg = 0;
-                        r += nwaves;
+                for (int i = 0; i < NPF; ++i) {
+                    pd[i] = -1;
+                    if (r < nrows) {
+                        load_vec(zz, yf, r, seg, pv[i], pd[i]);
+                        if (++seg == nseg) {
+                            seg = 0;
+                            r += nwaves;
+                        }
                     }
                 }
-            }
 #pragma unroll
-            for (int i = 0; i < NPF; ++i)
-                if (pd[i] >= 0) put(pv[i], pd[i]);
-        }
-        for (int h = tid; h < 2 * nrows; h += nthreads) {
-            VT v;
-            int d;
-            load_halo(zz, h, v, d);
-            put(v, d);
+                for (int i = 0; i < NPF; ++i)
+                    if (pd[i] >= 0) put(pv[i], pd[i]);
+            }
+            for (int h = tid; h < 2 * nrows; h += nthreads) {
+                VT v;
+                int d;
+                load_halo(zz, yf, h, v, d);
+                put(v, d);
+            }
         }
     }
     __syncthreads();
@@ -892,10 +929,6 @@ __global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
     const int groups = a.rows_per_wave / RL;
     const int rl0 = (wave * groups + g) * RL;
     const bool lane_ok = g < groups;
-    bool rowok[RL];
-#pragma unroll
-    for (int q = 0; q < RL; ++q) rowok[q] = lane_ok && (rl0 + q < Ract);
-    const bool active = rowok[0];
     const int cb_off = (rl0 + 1) * pitch + j * (CX + PADE);
 
     const T ihx2 = (T)md.ih2[0], ihy2 = (T)md.ih2[1], ihz2 = (T)md.ih2[2];
@@ -906,38 +939,45 @@ __global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
     double pF = 0.0, pS = 0.0, pG = 0.0;
     for (int u = 0; u < nunits; ++u) {
         const int z = zbase + u;
+        const int y0 = unit_y0(u);
+        const int Ract = min(a.R, ny - y0);
         const bool has_next = u + 1 < nunits;
-        // rows of the plane the next unit adds start loading now (the host
-        // guarantees that a wavefront's share of one plane fits NPF vectors
-        // per lane and the halos one vector per thread)
+        bool rowok[RL];
+#pragma unroll
+        for (int q = 0; q < RL; ++q) rowok[q] = lane_ok && (rl0 + q < Ract);
+        const bool active = rowok[0];
+        // the rows the next unit adds start loading now (the host guarantees
+        // that a wavefront's share of them fits NPF vectors per lane and the
+        // halos one vector per thread)
         VT pv[NPF], ph;
         int pd[NPF], phd = -1;
-        {
-            const int zz = z + 1 + xhi;
+        if (has_next) {
+            const int zz = (DIM == 3) ? z + 1 + xhi : 0;
+            const int yf = unit_y0(u + 1), nrows = unit_rows(u + 1);
             int r = wv, seg = 0;  // wave-uniform cursor (row, segment)
 #pragma unroll
             for (int i = 0; i < NPF; ++i) {
                 pd[i] = -1;
-                if (has_next && r < nrows) {
-                    load_vec(zz, r, seg, pv[i], pd[i]);
+                if (r < nrows) {
+                    load_vec(zz, yf, r, seg, pv[i], pd[i]);
                     if (++seg == nseg) {
                         seg = 0;
                         r += nwaves;
                     }
                 }
             }
-            if (has_next && tid < 2 * nrows) load_halo(zz, tid, ph, phd);
+            if (tid < 2 * nrows) load_halo(zz, yf, tid, ph, phd);
         }
 
-        // ring slots of planes z-1 .. z+2
-        const int s0 = (u & 3) * planeStride + cb_off;
-        const int s1 = ((u + 1) & 3) * planeStride + cb_off;
-        const int s2 = ((u + 2) & 3) * planeStride + cb_off;
-        const int s3 = ((u + 3) & 3) * planeStride + cb_off;
+        // staged planes z-1 .. z+2 (3D ring slots); 2D uses slot 0 only
+        const int s0 = (DIM == 3 ? (u & 3) * planeStride : 0) + cb_off;
+        const int s1 = (DIM == 3 ? ((u + 1) & 3) * planeStride : 0) + cb_off;
+        const int s2 = (DIM == 3 ? ((u + 2) & 3) * planeStride : 0) + cb_off;
+        const int s3 = (DIM == 3 ? ((u + 3) & 3) * planeStride : 0) + cb_off;
 #define AT(dz, dy, m) \
     sC[((dz) < 0 ? s0 : (dz) == 0 ? s1 : (dz) == 1 ? s2 : s3) + (dy) * pitch + (m) + ((m) / CX) * PADE]
 
-        // every lane forms the RHS (see the single-plane kernel)
+        // every lane forms the RHS (see the single-unit kernel)
         T v[RL][CX];
         if (solve) {
             auto at = [&](int dz, int dy, int m) { return AT(dz, dy, m); };
@@ -945,7 +985,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
             for (int k = 0; k < CX; ++k)
 #pragma unroll
                 for (int q = 0; q < RL; ++q)
-                    v[q][k] = rhs_site<T, 3>(at, q, k + HALO, ihx2, ihy2, ihz2, dt, tg, cxy, cxz, cyz);
+                    v[q][k] = rhs_site<T, DIM>(at, q, k + HALO, ihx2, ihy2, ihz2, dt, tg, cxy, cxz, cyz);
         }
         if (active) {
             if (needF) {
@@ -961,8 +1001,11 @@ __global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
                         const double c = (double)AT(0, q, m0);
                         const double ex = (double)AT(0, q, m0 + 1) - c;
                         const double ey = (double)AT(0, q + 1, m0) - c;
-                        const double ez = (double)AT(1, q, m0) - c;
-                        const double gr = ex * ex * dx2 + ey * ey * dy2 + ez * ez * dz2;
+                        double gr = ex * ex * dx2 + ey * ey * dy2;
+                        if (DIM == 3) {
+                            const double ez = (double)AT(1, q, m0) - c;
+                            gr += ez * ez * dz2;
+                        }
                         const double qq = c * c - 1.0;
                         pF += cbulk * qq * qq + hg * gr;
                         pS += c;
@@ -974,10 +1017,10 @@ __global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
                 const double dx2 = md.ih2[0], dy2 = md.ih2[1], dz2 = md.ih2[2];
                 auto MU = [&](int dz, int dy, int m) -> double {
                     const double uu = (double)AT(dz, dy, m);
-                    const double l =
-                        ((double)AT(dz, dy, m + 1) - 2.0 * uu + (double)AT(dz, dy, m - 1)) * dx2 +
-                        ((double)AT(dz, dy + 1, m) - 2.0 * uu + (double)AT(dz, dy - 1, m)) * dy2 +
-                        ((double)AT(dz + 1, dy, m) - 2.0 * uu + (double)AT(dz - 1, dy, m)) * dz2;
+                    double l = ((double)AT(dz, dy, m + 1) - 2.0 * uu + (double)AT(dz, dy, m - 1)) * dx2 +
+                               ((double)AT(dz, dy + 1, m) - 2.0 * uu + (double)AT(dz, dy - 1, m)) * dy2;
+                    if (DIM == 3)
+                        l += ((double)AT(dz + 1, dy, m) - 2.0 * uu + (double)AT(dz - 1, dy, m)) * dz2;
                     return uu * uu * uu - uu - gam * l;
                 };
 #pragma unroll
@@ -989,8 +1032,12 @@ __global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
                         const double mu = MU(0, q, m0);
                         const double gx = MU(0, q, m0 + 1) - mu;
                         const double gy = MU(0, q + 1, m0) - mu;
-                        const double gz = MU(1, q, m0) - mu;
-                        pG += gx * gx * dx2 + gy * gy * dy2 + gz * gz * dz2;
+                        double qq = gx * gx * dx2 + gy * gy * dy2;
+                        if (DIM == 3) {
+                            const double gz = MU(1, q, m0) - mu;
+                            qq += gz * gz * dz2;
+                        }
+                        pG += qq;
                     }
                 }
             }
@@ -1037,19 +1084,26 @@ __global__ void __launch_bounds__(kPassAThreads) passA_ring_kernel(PassAArgs a)
             scan_bwd_wave<T, RL>(e0, e1, j, P, SL, cf);
 #pragma unroll
             for (int q = 0; q < RL; ++q) bwd_true(v[q], cf.a1, cf.a2, e0[q], e1[q], cf.ik, mean[q]);
-            // each lane stores its own chunk of every line it holds
+            if (DIM == 3) {
+                // each lane stores its own chunk of every line it holds
 #pragma unroll
-            for (int q = 0; q < RL; ++q) {
-                if (!rowok[q]) continue;
-                T* dst = Wout + ((int64_t)z * ny + y0 + rl0 + q) * nx + j * CX;
+                for (int q = 0; q < RL; ++q) {
+                    if (!rowok[q]) continue;
+                    T* dst = Wout + ((int64_t)z * ny + y0 + rl0 + q) * nx + j * CX;
 #pragma unroll
-                for (int k = 0; k < CX; k += VEC)
-                    *reinterpret_cast<VT*>(dst + k) = vec_make<T>(&v[q][k]);
+                    for (int k = 0; k < CX; k += VEC)
+                        *reinterpret_cast<VT*>(dst + k) = vec_make<T>(&v[q][k]);
+                }
             }
+        }
+        if (DIM == 2 && solve) {
+            __syncthreads();  // every read of the staged rows is done
+            write_back<T, CX, RL>(sC + pitch, pitch, v, rowok, rl0, j, wv, lane, a.rows_per_wave, Ract, nvec,
+                                  Wout + (int64_t)y0 * nx, nx);
         }
 
         if (has_next) {
-            __syncthreads();  // every read of the slot the new plane replaces is done
+            __syncthreads();  // every read of the rows the new ones replace is done
 #pragma unroll
             for (int i = 0; i < NPF; ++i)
                 if (pd[i] >= 0) put(pv[i], pd[i]);
@@ -1304,11 +1358,11 @@ static hipError_t launchA(const PassAArgs& a, size_t lds, hipStream_t s, hipEven
     return launch_k(k, (unsigned)a.nblocks, 64 * a.waves, lds, s, a, ev0, ev1);
 }
 
-template <typename T, int CX, int RL>
-static hipError_t launchRing(const PassAArgs& a, size_t lds, hipStream_t s, hipEvent_t ev0,
-                             hipEvent_t ev1)
+template <typename T, int DIM, int CX, int RL>
+static hipError_t launchMulti(const PassAArgs& a, size_t lds, hipStream_t s, hipEvent_t ev0,
+                              hipEvent_t ev1)
 {
-    auto k = passA_ring_kernel<T, CX, RL>;
+    auto k = passA_multi_kernel<T, DIM, CX, RL>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1320,17 +1374,17 @@ static hipError_t launchRing(const PassAArgs& a, size_t lds, hipStream_t s, hipE
 // (chunk length, lines per lane) pairs that are compiled
 #define CH_PASSA_SHAPES(X) \
     X(4, 1) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(4, 2) X(8, 2) X(16, 2) X(32, 2) X(4, 4) X(8, 4) X(16, 4)
-// ... and those of the 3D plane-ring variant
-#define CH_RING_SHAPES(X) X(4, 1) X(8, 1) X(16, 1) X(32, 1) X(4, 2) X(8, 2) X(16, 2)
+// ... and those of the several-units variant
+#define CH_MULTI_SHAPES(X) X(4, 1) X(8, 1) X(16, 1) X(32, 1) X(4, 2) X(8, 2) X(16, 2)
 
 template <typename T, int DIM>
 static hipError_t launchA_shape(int cx, int rl, int units, const PassAArgs& a, size_t lds,
                                 hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    if (DIM == 3 && units > 1) {
+    if (units > 1) {
 #define X(C, R) \
-    if (cx == C && rl == R) return launchRing<T, C, R>(a, lds, s, ev0, ev1);
-        CH_RING_SHAPES(X)
+    if (cx == C && rl == R) return launchMulti<T, DIM, C, R>(a, lds, s, ev0, ev1);
+        CH_MULTI_SHAPES(X)
 #undef X
         return hipErrorInvalidValue;
     }
@@ -1346,10 +1400,9 @@ bool passA_has(int dim, int cx, int rl, int units)
 {
     if (dim != 2 && dim != 3) return false;
     if (units > 1) {
-        if (dim != 3) return false;
 #define X(C, R) \
     if (cx == C && rl == R) return true;
-        CH_RING_SHAPES(X)
+        CH_MULTI_SHAPES(X)
 #undef X
         return false;
     }

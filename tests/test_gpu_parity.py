@@ -131,7 +131,8 @@ def _all_tiles(ens, cls, n, prec):
                 P = ny // cy
                 for b in (1, 2, 4, 8, 16, 32, 64):
                     if nx % b == 0 and b * P <= 512:
-                        out.append((cx, rl, waves, 1, cy, b))
+                        for units in (1, 2, 3):
+                            out.append((cx, rl, waves, units, cy, b))
     return out
 
 
@@ -141,7 +142,9 @@ def test_every_tile_shape_parity_2d():
     N = 12
     Cref = oracle.step(_ref_field(d, (64, 128)), gamma, dt, N)
     ens = Ensemble([d], prec=CH_F64, cadence=5, max_samples=N // 5 + 1)
+    _, S = oracle.run_series(_ref_field(d, (64, 128)), gamma, dt, N, K=5)
     tried = 0
+    seen_units = set()
     for cx, rl, waves, units, cy, b in _all_tiles(ens, 0, n, CH_F64):
         try:
             ens.set_tiles(0, cx, rl, waves, units, cy, b)
@@ -151,11 +154,10 @@ def test_every_tile_shape_parity_2d():
         ens.step(N)
         err = float(np.abs(ens.get_field(0) - Cref).max())
         assert err <= TOL, ((cx, rl, waves, units, cy, b), err)
+        _check_series(ens.beta_series(0), S)
         tried += 1
-    assert tried >= 80
-    # several planes per block is a 3D-only variant
-    with pytest.raises(ChError):
-        ens.set_tiles(0, 16, 1, 4, 2, 8, 8)
+        seen_units.add(units)
+    assert tried >= 80 and seen_units == {1, 2, 3}
     ens.close()
 
 
@@ -187,6 +189,33 @@ def test_every_tile_shape_parity_3d():
                         tried += 1
                         seen_units.add(units)
     assert tried >= 40 and seen_units == {1, 3, 8, 24}
+    ens.close()
+
+
+def test_several_bands_fp32_2d_ragged():
+    """FP32 bulk, 2D, several y-bands per block, with a ragged last band (72
+    lines in bands of 16 or 32) and a ragged last group of bands, against the
+    oracle from the same FP32-rounded field; sample steps included."""
+    n, gamma, dt = (256, 72), 0.01, 1e-3
+    d = make_desc(n, gamma, dt, c0=-0.1, noise=0.1, seed=24)
+    N = 12
+    C0 = _ref_field(d, (72, 256)).astype(np.float32).astype(np.float64)
+    Cref = oracle.step(C0, gamma, dt, N)
+    ens = Ensemble([d], prec=CH_F32_BULK, cadence=5, max_samples=N // 5 + 1)
+    tried = 0
+    for cx, rl in ((4, 1), (8, 1), (16, 1), (32, 1), (8, 2), (16, 2)):
+        for waves in (2, 4):
+            for units in (2, 3):
+                try:
+                    ens.set_tiles(0, cx, rl, waves, units, 8, 8)
+                except ChError:
+                    continue
+                ens.init_random()
+                ens.step(N)
+                err = float(np.abs(ens.get_field(0) - Cref).max())
+                assert err <= 2e-5, ((cx, rl, waves, units), err)
+                tried += 1
+    assert tried >= 12
     ens.close()
 
 
