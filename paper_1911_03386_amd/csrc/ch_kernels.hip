@@ -948,25 +948,30 @@ __global__ void __launch_bounds__(kPassAThreads) passA_multi_kernel(PassAArgs a)
         const bool active = rowok[0];
         // the rows the next unit adds start loading now (the host guarantees
         // that a wavefront's share of them fits NPF vectors per lane and the
-        // halos one vector per thread)
+        // halos one vector per thread); their LDS places are recomputed when
+        // they are written, from the same wave-uniform cursor
+        const int pf_z = (DIM == 3) ? z + 1 + xhi : 0;
+        const int pf_y = has_next ? unit_y0(u + 1) : 0;
+        const int pf_rows = has_next ? unit_rows(u + 1) : 0;
         VT pv[NPF], ph;
-        int pd[NPF], phd = -1;
-        if (has_next) {
-            const int zz = (DIM == 3) ? z + 1 + xhi : 0;
-            const int yf = unit_y0(u + 1), nrows = unit_rows(u + 1);
+        {
             int r = wv, seg = 0;  // wave-uniform cursor (row, segment)
 #pragma unroll
             for (int i = 0; i < NPF; ++i) {
-                pd[i] = -1;
-                if (r < nrows) {
-                    load_vec(zz, yf, r, seg, pv[i], pd[i]);
+                if (r < pf_rows) {
+                    const int xi = seg * 64 + lane;
+                    if (xi < nvec)
+                        pv[i] = *reinterpret_cast<const VT*>(row_of(pf_z, pf_y, r) + (uint32_t)xi * VEC);
                     if (++seg == nseg) {
                         seg = 0;
                         r += nwaves;
                     }
                 }
             }
-            if (tid < 2 * nrows) load_halo(zz, yf, tid, ph, phd);
+            if (tid < 2 * pf_rows) {
+                int d;
+                load_halo(pf_z, pf_y, tid, ph, d);
+            }
         }
 
         // staged planes z-1 .. z+2 (3D ring slots); 2D uses slot 0 only
@@ -1104,10 +1109,27 @@ __global__ void __launch_bounds__(kPassAThreads) passA_multi_kernel(PassAArgs a)
 
         if (has_next) {
             __syncthreads();  // every read of the rows the new ones replace is done
+            const int base = slot_of(pf_z);
+            int r = wv, seg = 0;  // the cursor of the loads above
 #pragma unroll
-            for (int i = 0; i < NPF; ++i)
-                if (pd[i] >= 0) put(pv[i], pd[i]);
-            if (phd >= 0) put(ph, phd);
+            for (int i = 0; i < NPF; ++i) {
+                if (r < pf_rows) {
+                    const int xi = seg * 64 + lane;
+                    if (xi < nvec) {
+                        const uint32_t xx = (uint32_t)xi * VEC + HALO;
+                        put(pv[i], base + r * pitch + (int)(xx + xx / CX * PADE));
+                    }
+                    if (++seg == nseg) {
+                        seg = 0;
+                        r += nwaves;
+                    }
+                }
+            }
+            if (tid < 2 * pf_rows) {
+                const int hr = tid >> 1;
+                const int xx = (tid & 1) ? nx + HALO : 0;
+                put(ph, base + hr * pitch + xx + (xx / CX) * PADE);
+            }
             __syncthreads();
         }
     }
