@@ -42,7 +42,7 @@ def parse():
     p.add_argument("--no-autotune", dest="autotune", action="store_false",
                    help="keep the default tile shapes (autotuning reads the cache first)")
     p.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1911_03386_amd", "tune_cache.txt"))
-    p.add_argument("--graph-steps", type=int, default=16)
+    p.add_argument("--graph-steps", type=int, default=64, help="steps per captured HIP graph")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of known size (for HBM counter calibration)")
     return p.parse_args()
@@ -159,7 +159,10 @@ def main():
     S = wl.sites
     value = S * steps / (r["gpu_ms"] / 1e3) / 1e9
     word = 4 if wl.prec == CH_F32_BULK else 8
-    # per launch each pass reads the field once and writes it once
+    # Each pass reads the field once and writes it once.  A "launch" of a pass
+    # is that pass over the whole batch: one kernel per size class, each timed
+    # alone with its own start/end timestamps (the timed steps run the classes
+    # concurrently on separate streams; step_frac is the whole-step figure).
     kinds = ["x_pass", "y_pass", "z_pass"]
     kms = r["kernel_ms"]
     dom = max(range(3), key=lambda i: kms[i])
@@ -191,6 +194,7 @@ def main():
             "traffic": traffic,
             "alg_bytes_per_launch": alg_bytes,
             "ms_per_launch": {k: round(v, 5) for k, v in zip(kinds, kms)},
+            "classes": len(r["plan"].strip().splitlines()),
             "step_frac": round(S * 4 * word * (1.5 if wl.descs[0].dim == 3 else 1.0)
                                / (r["gpu_ms"] / steps / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
         },

@@ -37,6 +37,11 @@
  *    graphs that reference the workspace).
  *  - Work is enqueued on the caller's HIP stream given to ch_create (NULL =
  *    the null stream).  Calls that return data to the host synchronise it.
+ *    With several size classes, ch_step runs the classes on up to four
+ *    streams: up to three more streams (default priority, created by
+ *    ch_create, destroyed by ch_destroy) are forked from the caller's stream
+ *    at the start of each ch_step call or graph replay and joined back into
+ *    it at the end, so the caller's stream orders all work as usual.
  *  - Asynchronous device faults surface at the next synchronising call as
  *    CH_EDEVICE.  A non-finite F sets a sticky per-member flag reported as
  *    CH_ENONFINITE by ch_energy and ch_beta_series.
@@ -150,13 +155,19 @@ ch_status ch_beta_series(ch_ctx* ctx, int32_t member, double* t, double* F, doub
 
 /* Tile shapes.  ch_autotune times every valid tile shape of every size class
  * on the device (using the workspace's scratch field only: the state and the
- * series are untouched) and keeps the fastest.  cache_path (may be NULL) is a
- * text file of earlier choices keyed by GPU architecture, shape and
- * precision; it is read first and rewritten with the results. */
+ * series are untouched) and keeps the fastest.  With several classes it then
+ * times the best few shapes of each class together, as whole steps of all
+ * classes running concurrently, and keeps the fastest combination.
+ * cache_path (may be NULL) is a text file of earlier choices keyed by GPU
+ * architecture, shape, member count and precision; it is read first and
+ * rewritten with the results. */
 ch_status ch_autotune(ch_ctx* ctx, const char* cache_path);
 
-/* Number of size classes (members grouped by dimension and grid shape, in
- * order of first appearance) and explicit tile shapes for one class.  The
+/* Number of size classes and explicit tile shapes for one class.  Members
+ * are grouped by dimension and grid shape, in order of first appearance; while
+ * there are fewer than four classes, the largest class with at least 8
+ * members is split into two classes of consecutive members.  Classes are
+ * independent and run concurrently on separate streams.  The
  * RHS + x-solve pass: cx = elements per lane of an x-line, rl = x-lines per
  * lane, waves = wavefronts per block, units = work units a block walks
  * through, loading the next one while it computes the current one (y-bands

@@ -34,6 +34,11 @@ bool is_live(const void* p)
 
 constexpr size_t kAlign = 256;
 constexpr size_t kLdsLimit = 160 * 1024 - 1024;  // gfx950: 160 KiB per workgroup, minus statics
+// The size classes of a step run on up to kMaxStreams streams; a class is
+// split in two while there are fewer classes than streams and it has at
+// least 2 * kMinSplit members.
+constexpr int kMaxStreams = 4;
+constexpr int kMinSplit = 4;
 
 size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 
@@ -321,6 +326,22 @@ void build_classes(const ch_member_desc* members, int32_t m, std::vector<ClassPl
         }
         classes[it->second].members.push_back(i);
     }
+    // Split the largest classes into consecutive runs of members, so that the
+    // classes of a step can overlap on separate streams: one class's
+    // latency-bound RHS pass with another's bandwidth-bound column sweeps.
+    while ((int)classes.size() < kMaxStreams) {
+        int big = -1;
+        for (int c = 0; c < (int)classes.size(); ++c)
+            if (classes[c].members.size() >= 2 * (size_t)kMinSplit &&
+                (big < 0 || classes[c].members.size() > classes[big].members.size()))
+                big = c;
+        if (big < 0) break;
+        ClassPlan second = classes[big];
+        const size_t half = classes[big].members.size() / 2;
+        second.members.assign(classes[big].members.begin() + half, classes[big].members.end());
+        classes[big].members.resize(half);
+        classes.insert(classes.begin() + big + 1, second);
+    }
 }
 
 bool default_plans(std::vector<ClassPlan>& classes, int prec)
@@ -384,6 +405,12 @@ struct ch_ctx {
     int prec = 0, conv = 0, K = 10;
     int64_t max_samples = 1;
     hipStream_t stream = nullptr;
+    // streams of the other size classes (class ci runs on stream ci mod
+    // (1 + aux.size()), stream 0 being `stream`), forked from and joined back
+    // into `stream` in every step
+    std::vector<hipStream_t> aux;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
     int device = 0;
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -551,35 +578,100 @@ ColArgs col_args(ch_ctx* ctx, int ci, int axis, const void* src, void* dst, bool
     return a;
 }
 
-hipError_t launch_A(ch_ctx* ctx, int ci, int mode, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
+hipError_t launch_A(ch_ctx* ctx, int ci, int mode, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                    hipStream_t s = nullptr)
 {
     ClassPlan& c = ctx->classes[ci];
     PassAArgs a = passA_args(ctx, ci, mode);
-    return launch_passA(ctx->prec, c.dim, c.cx, c.rl, c.units, a, c.ldsA, ctx->stream, ev0, ev1);
+    return launch_passA(ctx->prec, c.dim, c.cx, c.rl, c.units, a, c.ldsA, s ? s : ctx->stream, ev0, ev1);
 }
 
 // the column sweeps of one step: 2D  w -> C ;  3D  w -> w (y), w -> C (z)
 hipError_t launch_cols(ch_ctx* ctx, int ci, int axis, hipEvent_t ev0 = nullptr,
-                       hipEvent_t ev1 = nullptr)
+                       hipEvent_t ev1 = nullptr, hipStream_t s = nullptr)
 {
     ClassPlan& c = ctx->classes[ci];
     void* W = ctx->d_W();
     void* C = ctx->d_C();
     const bool last = (axis == c.dim - 1);
     return launch_col(ctx->prec, c.col[axis].cy, col_args(ctx, ci, axis, W, last ? C : W, last),
-                      ctx->stream, ev0, ev1);
+                      s ? s : ctx->stream, ev0, ev1);
 }
 
-hipError_t enqueue_step(ch_ctx* ctx)
+void release_streams(ch_ctx* ctx)
+{
+    for (hipStream_t s : ctx->aux) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    }
+    for (hipEvent_t ev : ctx->ev_join) (void)hipEventDestroy(ev);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    ctx->aux.clear();
+    ctx->ev_join.clear();
+    ctx->ev_fork = nullptr;
+}
+
+// nsteps steps.  Classes are independent (own members, partials, step
+// counter), so each class runs all its steps in order on its own stream; the
+// other streams are forked from the context stream first and joined back into
+// it at the end.  Classes on different streams drift apart in phase, so one
+// class's latency-bound RHS pass overlaps another's bandwidth-bound sweeps.
+hipError_t enqueue_steps(ch_ctx* ctx, int64_t nsteps)
 {
     const int nc = (int)ctx->classes.size();
+    const int ns = 1 + (int)ctx->aux.size();
     hipError_t e;
-    for (int ci = 0; ci < nc; ++ci)
-        if ((e = launch_A(ctx, ci, MODE_STEP)) != hipSuccess) return e;
-    for (int ci = 0; ci < nc; ++ci)
-        if ((e = launch_cols(ctx, ci, 1)) != hipSuccess) return e;
-    for (int ci = 0; ci < nc; ++ci)
-        if (ctx->classes[ci].dim == 3 && (e = launch_cols(ctx, ci, 2)) != hipSuccess) return e;
+    if (ns > 1) {
+        if ((e = hipEventRecord(ctx->ev_fork, ctx->stream)) != hipSuccess) return e;
+        for (hipStream_t s : ctx->aux)
+            if ((e = hipStreamWaitEvent(s, ctx->ev_fork, 0)) != hipSuccess) return e;
+    }
+    for (int ci = 0; ci < nc; ++ci) {
+        hipStream_t s = (ci % ns == 0) ? ctx->stream : ctx->aux[ci % ns - 1];
+        for (int64_t i = 0; i < nsteps; ++i) {
+            if ((e = launch_A(ctx, ci, MODE_STEP, nullptr, nullptr, s)) != hipSuccess) return e;
+            if ((e = launch_cols(ctx, ci, 1, nullptr, nullptr, s)) != hipSuccess) return e;
+            if (ctx->classes[ci].dim == 3 && (e = launch_cols(ctx, ci, 2, nullptr, nullptr, s)) != hipSuccess)
+                return e;
+        }
+    }
+    for (int i = 0; i + 1 < ns; ++i) {
+        if ((e = hipEventRecord(ctx->ev_join[i], ctx->aux[i])) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(ctx->stream, ctx->ev_join[i], 0)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// nsteps stand-in steps for tuning, with the stream structure of
+// enqueue_steps: pass A in timing mode (reads C, writes the scratch field w,
+// no diagnostics) and the column sweeps in place on w.  The state, the step
+// counters and the series are untouched.
+hipError_t enqueue_timing_steps(ch_ctx* ctx, int nsteps)
+{
+    const int nc = (int)ctx->classes.size();
+    const int ns = 1 + (int)ctx->aux.size();
+    void* W = ctx->d_W();
+    hipError_t e;
+    if (ns > 1) {
+        if ((e = hipEventRecord(ctx->ev_fork, ctx->stream)) != hipSuccess) return e;
+        for (hipStream_t s : ctx->aux)
+            if ((e = hipStreamWaitEvent(s, ctx->ev_fork, 0)) != hipSuccess) return e;
+    }
+    for (int ci = 0; ci < nc; ++ci) {
+        hipStream_t s = (ci % ns == 0) ? ctx->stream : ctx->aux[ci % ns - 1];
+        const ClassPlan& c = ctx->classes[ci];
+        for (int i = 0; i < nsteps; ++i) {
+            if ((e = launch_A(ctx, ci, MODE_TIMING, nullptr, nullptr, s)) != hipSuccess) return e;
+            for (int axis = 1; axis < c.dim; ++axis)
+                if ((e = launch_col(ctx->prec, c.col[axis].cy, col_args(ctx, ci, axis, W, W, false), s)) !=
+                    hipSuccess)
+                    return e;
+        }
+    }
+    for (int i = 0; i + 1 < ns; ++i) {
+        if ((e = hipEventRecord(ctx->ev_join[i], ctx->aux[i])) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(ctx->stream, ctx->ev_join[i], 0)) != hipSuccess) return e;
+    }
     return hipSuccess;
 }
 
@@ -607,8 +699,7 @@ ch_status ensure_graph(ch_ctx* ctx, int steps)
     if (ctx->gexec && ctx->gexec_steps == steps) return CH_OK;
     drop_graph(ctx);
     HIPCHK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    for (int i = 0; i < steps && e == hipSuccess; ++i) e = enqueue_step(ctx);
+    hipError_t e = enqueue_steps(ctx, steps);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -751,10 +842,28 @@ ch_status ch_create(const ch_member_desc* members, int32_t m, ch_precision prec,
         size_t colon = ctx->arch.find(':');
         if (colon != std::string::npos) ctx->arch.resize(colon);
     }
+    const int nstreams = std::min<int>((int)ctx->classes.size(), kMaxStreams);
+    if (nstreams > 1) {
+        e = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
+        for (int i = 1; i < nstreams && e == hipSuccess; ++i) {
+            hipStream_t s = nullptr;
+            hipEvent_t ev = nullptr;
+            e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+            if (e == hipSuccess) ctx->aux.push_back(s);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) ctx->ev_join.push_back(ev);
+        }
+        if (e != hipSuccess) {
+            release_streams(ctx);
+            delete ctx;
+            return fail(nullptr, CH_EDEVICE, "stream creation failed: %s", hipGetErrorString(e));
+        }
+    }
     fill_member_table(ctx);
     st = upload_tables(ctx);
     if (st != CH_OK) {
         g_err = ctx->err;
+        release_streams(ctx);
         delete ctx;
         return st;
     }
@@ -769,6 +878,7 @@ ch_status ch_create(const ch_member_desc* members, int32_t m, ch_precision prec,
                          ctx->d_series(), (int64_t)kSeriesSlots * m * max_samples, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
+        release_streams(ctx);
         delete ctx;
         return fail(nullptr, CH_EDEVICE, "initialisation failed: %s", hipGetErrorString(e));
     }
@@ -884,7 +994,7 @@ ch_status ch_step(ch_ctx* ctx, int64_t nsteps)
             left -= ctx->graph_steps;
         }
     }
-    for (; left > 0; --left) HIPCHK(ctx, enqueue_step(ctx));
+    if (left > 0) HIPCHK(ctx, enqueue_steps(ctx, left));
     ctx->step = target;
     if (nsteps > 0 && need_diag(target, ctx->K)) HIPCHK(ctx, enqueue_diag(ctx));
     return CH_OK;
@@ -1001,6 +1111,22 @@ ch_status ch_time_kernels(ch_ctx* ctx, int64_t nsteps, double* ms)
     return CH_OK;
 }
 
+namespace {
+// The fastest few shapes of one class key in isolation: [0] pass A
+// (cx, rl, waves, units), [1] y sweep (cy, b), [2] z sweep (cy, b).
+struct Shortlist {
+    static constexpr size_t kKeep[3] = {3, 2, 2};
+    std::vector<std::pair<float, std::vector<int>>> c[3];
+    void add(int k, float ms, std::vector<int> shape)
+    {
+        auto& v = c[k];
+        v.emplace_back(ms, std::move(shape));
+        std::sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+        if (v.size() > kKeep[k]) v.resize(kKeep[k]);
+    }
+};
+}  // namespace
+
 ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
 {
     ch_status st = check_ctx(ctx);
@@ -1040,6 +1166,33 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
         }
         return hipSuccess;
     };
+    // whole stand-in steps of all classes (one graph of 16, best of 3 replays)
+    auto time_steps = [&](float& ms) -> hipError_t {
+        const int n = 16;
+        hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        e = enqueue_timing_steps(ctx, n);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
+        if (e == hipSuccess) e = e2;
+        hipGraphExec_t ex = nullptr;
+        if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphLaunch(ex, ctx->stream);
+        ms = 1e30f;
+        for (int b = 0; b < 3 && e == hipSuccess; ++b) {
+            if ((e = hipEventRecord(e0, ctx->stream)) != hipSuccess) break;
+            if ((e = hipGraphLaunch(ex, ctx->stream)) != hipSuccess) break;
+            if ((e = hipEventRecord(e1, ctx->stream)) != hipSuccess) break;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+            float t = 0;
+            if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) break;
+            ms = std::min(ms, t / n);
+        }
+        if (ex) (void)hipGraphExecDestroy(ex);
+        if (g) (void)hipGraphDestroy(g);
+        return e;
+    };
+    std::map<std::string, Shortlist> shortlist;  // keys tuned in this call
     hipError_t err = hipSuccess;
     for (int ci = 0; ci < (int)ctx->classes.size() && err == hipSuccess; ++ci) {
         ClassPlan& c = ctx->classes[ci];
@@ -1059,6 +1212,7 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
         // pass A candidates (timing mode: reads C, writes the scratch field)
         float best = 1e30f;
         int bcx = c.cx, brl = c.rl, bw = c.waves, bu = c.units;
+        Shortlist& sl = shortlist[key];
         const int unit_opts_2d[] = {1, 2, 4};
         const int unit_opts_3d[] = {1, 4, 8, 16, 32};
         const int* uo = c.dim == 3 ? unit_opts_3d : unit_opts_2d;
@@ -1079,6 +1233,7 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
                         float ms = 0;
                         err = time_it([&] { return launch_A(ctx, ci, MODE_TIMING); }, ms);
                         if (err != hipSuccess) break;
+                        sl.add(0, ms, {cx, rl, waves, units});
                         if (ms < best) {
                             best = ms;
                             bcx = cx;
@@ -1119,6 +1274,7 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
                         },
                         ms);
                     if (err != hipSuccess) break;
+                    sl.add(axis, ms, {cy, b});
                     if (ms < bestc) {
                         bestc = ms;
                         bcy = cy;
@@ -1132,6 +1288,60 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
         }
         cache[key] = {c.cx, c.rl, c.waves, c.units, c.col[1].cy, c.col[1].b,
                       c.dim == 3 ? c.col[2].cy : 0, c.dim == 3 ? c.col[2].b : 0};
+    }
+    // Stage 2.  With several classes the steps of different classes overlap
+    // on separate streams, and the fastest shapes in isolation need not be
+    // the fastest together.  For each newly tuned class key in turn, every
+    // combination of its short-listed shapes is applied to all classes with
+    // that key and whole stand-in steps of all classes are timed together.
+    // (the legacy null stream cannot be captured: no stage 2 there)
+    if (err == hipSuccess && ctx->classes.size() > 1 && !shortlist.empty() && ctx->stream != nullptr) {
+        for (auto& kv : shortlist) {
+            const std::string& key = kv.first;
+            const Shortlist& sl = kv.second;
+            std::vector<int> idx;
+            for (int ci = 0; ci < (int)ctx->classes.size(); ++ci)
+                if (class_key(ctx, ctx->classes[ci]) == key) idx.push_back(ci);
+            const int dim = ctx->classes[idx[0]].dim;
+            const size_t nz = dim == 3 ? sl.c[2].size() : 1;
+            float bestj = 1e30f;
+            std::vector<ClassPlan> bestp;
+            for (size_t ia = 0; ia < sl.c[0].size() && err == hipSuccess; ++ia)
+                for (size_t iy = 0; iy < sl.c[1].size() && err == hipSuccess; ++iy)
+                    for (size_t iz = 0; iz < nz && err == hipSuccess; ++iz) {
+                        const std::vector<int>& A = sl.c[0][ia].second;
+                        const std::vector<int>& Y = sl.c[1][iy].second;
+                        std::vector<ClassPlan> saved, trial;
+                        bool ok = true;
+                        for (int ci : idx) {
+                            ClassPlan t = ctx->classes[ci];
+                            ok = ok && planA(t, ctx->prec, A[0], A[1], A[2], A[3]) &&
+                                 planCol(t, ctx->prec, 1, Y[0], Y[1]) &&
+                                 (dim == 2 || planCol(t, ctx->prec, 2, sl.c[2][iz].second[0],
+                                                      sl.c[2][iz].second[1]));
+                            trial.push_back(t);
+                            saved.push_back(ctx->classes[ci]);
+                        }
+                        if (!ok) continue;
+                        for (size_t k = 0; k < idx.size(); ++k) ctx->classes[idx[k]] = trial[k];
+                        fill_member_table(ctx);
+                        if ((st = upload_tables(ctx)) != CH_OK) return st;
+                        float ms = 0;
+                        err = time_steps(ms);
+                        if (err == hipSuccess && ms < bestj) {
+                            bestj = ms;
+                            bestp = trial;
+                        }
+                        for (size_t k = 0; k < idx.size(); ++k) ctx->classes[idx[k]] = saved[k];
+                    }
+            if (err != hipSuccess) break;
+            if (!bestp.empty()) {
+                for (size_t k = 0; k < idx.size(); ++k) ctx->classes[idx[k]] = bestp[k];
+                const ClassPlan& c = bestp[0];
+                cache[key] = {c.cx, c.rl, c.waves, c.units, c.col[1].cy, c.col[1].b,
+                              c.dim == 3 ? c.col[2].cy : 0, c.dim == 3 ? c.col[2].b : 0};
+            }
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1188,6 +1398,7 @@ ch_status ch_destroy(ch_ctx* ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     drop_graph(ctx);
+    release_streams(ctx);
     delete ctx;
     return CH_OK;
 }

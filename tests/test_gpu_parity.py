@@ -136,6 +136,34 @@ def _all_tiles(ens, cls, n, prec):
     return out
 
 
+def test_split_classes_on_streams_parity():
+    """16 members of one shape: the class is split into 4 classes of 4 that run
+    on 4 streams.  Every member against the oracle; graph replays, direct
+    launches and a different graph length give bitwise equal results."""
+    descs = [make_desc((64, 32), 0.01, 1e-3, c0=0.05 * (m % 5) - 0.1, noise=0.1, seed=300 + m)
+             for m in range(16)]
+    N, K = 30, 10
+    runs = []
+    for gsteps in (16, 0, 7):
+        ens = Ensemble(descs, prec=CH_F64, cadence=K, max_samples=N // K + 1)
+        assert ens.num_classes() == 4
+        ens.set_graph_steps(gsteps)
+        ens.init_random()
+        ens.step(N)
+        runs.append((np.stack([ens.get_field(m) for m in range(16)]),
+                     np.stack([ens.beta_series(m) for m in range(16)])))
+        ens.close()
+    for C, S in runs[1:]:
+        np.testing.assert_array_equal(C, runs[0][0])
+        np.testing.assert_array_equal(S, runs[0][1])
+    for m in (0, 3, 4, 9, 15):
+        d = descs[m]
+        Cref, S = oracle.run_series(_ref_field(d, (32, 64)), d.gamma, d.dt, N, K=K)
+        err = float(np.abs(runs[0][0][m] - Cref).max())
+        assert err <= TOL, (m, err)
+        _check_series(runs[0][1][m], S)
+
+
 def test_every_tile_shape_parity_2d():
     n, gamma, dt = (128, 64), 0.01, 1e-3
     d = make_desc(n, gamma, dt, c0=0.1, noise=0.1, seed=21)
