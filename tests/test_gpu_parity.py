@@ -401,3 +401,23 @@ def test_autotune_keeps_parity_and_caches(tmp_path):
     assert ms[0] > 0 and ms[1] > 0 and ms[2] > 0
     assert ens2.step_count == 3
     ens2.close()
+
+
+def test_autotune_split_classes(tmp_path):
+    """8 members of one shape form 2 classes of 4 with one cache key; the joint
+    stage of the tuner times them together.  Parity afterwards."""
+    descs = [make_desc((64, 32), 0.01, 1e-3, c0=0.1, noise=0.1, seed=400 + m) for m in range(8)]
+    cache = str(tmp_path / "tune.txt")
+    N = 20
+    ens = Ensemble(descs, prec=CH_F64, cadence=10, max_samples=N // 10 + 1)
+    assert ens.num_classes() == 2
+    ens.autotune(cache)
+    text = open(cache).read()
+    assert text.count("\n") == 1 and ":f64:2D:64x32x1:m4 " in text
+    ens.init_random()
+    ens.step(N)
+    for m in (0, 5, 7):
+        d = descs[m]
+        ref = oracle.step(_ref_field(d, (32, 64)), d.gamma, d.dt, N)
+        assert float(np.abs(ens.get_field(m) - ref).max()) <= TOL
+    ens.close()
