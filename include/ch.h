@@ -198,6 +198,36 @@ ch_status ch_describe(const ch_ctx* ctx, char* buf, size_t cap);
  * nsteps. */
 ch_status ch_time_kernels(ch_ctx* ctx, int64_t nsteps, double* ms);
 
+/* Ensemble statistics of beta (the paper's eq. (mup) and eq. (beta0_stats),
+ * and the fit of the variance growth E(dbeta^2) = k t; Sections 3.3 and 4).
+ * members: nm member indices (NULL = all members); the selected members must
+ * share dt, so that sample j is at t_j = jK dt for all of them.  All three
+ * are computed on the device in FP64 with fixed-order sums (deterministic),
+ * from the recorded F series with the same beta as ch_beta_series, and
+ * synchronise.  CH_ENONFINITE if a selected member has a non-finite F.
+ *
+ * ch_ensemble_moments: for every recorded sample j = 0..count-1,
+ *   mu[j*pmax + 0]     = mu_1(t_j) = (1/M) sum_m beta_m(t_j),
+ *   mu[j*pmax + p - 1] = mu_p(t_j) = (1/M) sum_m (beta_m(t_j) - mu_1(t_j))^p,
+ * 1 <= pmax <= 8; t (may be NULL) receives t_j; mu holds cap*pmax doubles;
+ * *count = min(cap, floor(n_current/K) + 1).
+ *
+ * ch_ensemble_window: over the recorded samples with t1 <= t_j <= t2,
+ *   beta0 = (trapezoid integral of mu_1) / (t_last - t_first),
+ *   k     = sum t_j mu_2(t_j) / sum t_j^2 (least squares through the origin);
+ * NaN when the window holds fewer than two samples (beta0) or none (k).
+ *
+ * ch_beta_histogram: beta_m(t_j) over the members and the recorded samples
+ * with t1 <= t_j <= t2: counts[0] = values below lo, counts[1..nbins] = nbins
+ * equal bins of [lo, hi), counts[nbins+1] = values at or above hi (NaN not
+ * counted); 1 <= nbins <= 4096, counts holds nbins + 2 values. */
+ch_status ch_ensemble_moments(ch_ctx* ctx, const int32_t* members, int32_t nm, int32_t pmax, double* t,
+                              double* mu, int64_t cap, int64_t* count);
+ch_status ch_ensemble_window(ch_ctx* ctx, const int32_t* members, int32_t nm, double t1, double t2,
+                             double* beta0, double* k);
+ch_status ch_beta_histogram(ch_ctx* ctx, const int32_t* members, int32_t nm, double t1, double t2,
+                            double lo, double hi, int32_t nbins, uint64_t* counts);
+
 /* Release the context (synchronises its stream).  Later calls with the same
  * pointer return CH_ESTATE. */
 ch_status ch_destroy(ch_ctx* ctx);

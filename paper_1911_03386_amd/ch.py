@@ -31,6 +31,7 @@ EXPORTED = (
     "ch_get_step", "ch_set_step", "ch_step", "ch_energy", "ch_beta_series", "ch_autotune",
     "ch_set_graph_steps", "ch_describe", "ch_time_kernels", "ch_destroy", "ch_last_error",
     "ch_version", "ch_solver_coefficients", "ch_num_classes", "ch_set_tiles",
+    "ch_ensemble_moments", "ch_ensemble_window", "ch_beta_histogram",
 )
 
 
@@ -94,6 +95,13 @@ def load() -> ctypes.CDLL:
                                                   ctypes.c_int32, dp]),
         "ch_num_classes": (ctypes.c_int, [vp, P(ctypes.c_int32)]),
         "ch_set_tiles": (ctypes.c_int, [vp] + [ctypes.c_int32] * 9),
+        "ch_ensemble_moments": (ctypes.c_int, [vp, P(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32, dp,
+                                               dp, ctypes.c_int64, i64p]),
+        "ch_ensemble_window": (ctypes.c_int, [vp, P(ctypes.c_int32), ctypes.c_int32, ctypes.c_double,
+                                              ctypes.c_double, dp, dp]),
+        "ch_beta_histogram": (ctypes.c_int, [vp, P(ctypes.c_int32), ctypes.c_int32, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_int32, P(ctypes.c_uint64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -237,6 +245,46 @@ class Ensemble:
                                      ctypes.byref(count)), self.ctx)
         J = count.value
         return np.stack([c[:J] for c in cols], axis=1)
+
+    def _members(self, members):
+        if members is None:
+            return None, 0
+        sel = np.ascontiguousarray(members, dtype=np.int32)
+        return sel, len(sel)
+
+    def ensemble_moments(self, members=None, pmax: int = 4):
+        """(t, mu): t (J,), mu (J, pmax) with mu[:, 0] the ensemble mean of beta
+        and mu[:, p-1] its p-th central moment, over `members` (default all)."""
+        sel, nm = self._members(members)
+        cap = self.max_samples
+        t = np.empty(cap)
+        mu = np.empty(cap * pmax)
+        count = ctypes.c_int64()
+        mp = sel.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if sel is not None else None
+        _check(load().ch_ensemble_moments(self.ctx, mp, nm, pmax, _dp(t), _dp(mu), cap,
+                                          ctypes.byref(count)), self.ctx)
+        J = count.value
+        return t[:J], mu[:J * pmax].reshape(J, pmax)
+
+    def ensemble_window(self, t1: float, t2: float, members=None):
+        """(beta0, k): time average of the ensemble-mean beta over [t1, t2] and the
+        least-squares slope of its variance, mu_2 = k t."""
+        sel, nm = self._members(members)
+        b0, k = ctypes.c_double(), ctypes.c_double()
+        mp = sel.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if sel is not None else None
+        _check(load().ch_ensemble_window(self.ctx, mp, nm, t1, t2, ctypes.byref(b0), ctypes.byref(k)),
+               self.ctx)
+        return b0.value, k.value
+
+    def beta_histogram(self, t1: float, t2: float, lo: float, hi: float, nbins: int, members=None):
+        """Counts of beta over the members and samples with t in [t1, t2]:
+        [below lo, nbins bins of [lo, hi), at or above hi]."""
+        sel, nm = self._members(members)
+        counts = np.zeros(nbins + 2, dtype=np.uint64)
+        mp = sel.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if sel is not None else None
+        _check(load().ch_beta_histogram(self.ctx, mp, nm, t1, t2, lo, hi, nbins,
+                                        counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))), self.ctx)
+        return counts
 
     def autotune(self, cache_path: Optional[str] = None):
         _check(load().ch_autotune(self.ctx, cache_path.encode() if cache_path else None), self.ctx)

@@ -38,6 +38,7 @@ constexpr size_t kLdsLimit = 160 * 1024 - 1024;  // gfx950: 160 KiB per workgrou
 // split in two while there are fewer classes than streams and it has at
 // least 2 * kMinSplit members.
 constexpr int kMaxStreams = 4;
+constexpr int kMaxHistBins = 4096;
 constexpr int kMinSplit = 4;
 
 size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
@@ -64,6 +65,7 @@ struct ClassPlan {
 struct Layout {
     size_t off_mem = 0, off_C = 0, off_W = 0, off_steps = 0, off_nstamp = 0, off_flags = 0;
     size_t off_series = 0, off_energy = 0, off_beta = 0, total = 0;
+    size_t off_statm = 0, off_stat = 0, off_hist = 0;  // ensemble statistics
     int64_t total_elems = 0;
     std::vector<int64_t> moff;  // element offset per member
 };
@@ -395,6 +397,12 @@ void layout(const ch_member_desc* members, int32_t m, int prec, int64_t max_samp
     o = align_up(o + sizeof(double) * 4 * (size_t)m);
     L.off_beta = o;
     o = align_up(o + sizeof(double) * 6 * (size_t)max_samples);
+    L.off_statm = o;
+    o = align_up(o + sizeof(int32_t) * m);
+    L.off_stat = o;
+    o = align_up(o + sizeof(double) * (kMaxMoments * (size_t)max_samples + 2));
+    L.off_hist = o;
+    o = align_up(o + sizeof(uint64_t) * (kMaxHistBins + 2));
     L.total = o;
 }
 
@@ -434,6 +442,9 @@ struct ch_ctx {
     double* d_series() { return reinterpret_cast<double*>(ws + L.off_series); }
     double* d_energy() { return reinterpret_cast<double*>(ws + L.off_energy); }
     double* d_beta() { return reinterpret_cast<double*>(ws + L.off_beta); }
+    int32_t* d_statm() { return reinterpret_cast<int32_t*>(ws + L.off_statm); }
+    double* d_stat() { return reinterpret_cast<double*>(ws + L.off_stat); }
+    uint64_t* d_hist() { return reinterpret_cast<uint64_t*>(ws + L.off_hist); }
 };
 
 namespace {
@@ -1400,6 +1411,134 @@ ch_status ch_destroy(ch_ctx* ctx)
     drop_graph(ctx);
     release_streams(ctx);
     delete ctx;
+    return CH_OK;
+}
+
+// ---- ensemble statistics of beta ---------------------------------------------
+
+namespace {
+// Validate a member selection (NULL = all members), require a common dt, copy
+// the list to the workspace and report the recorded sample count.
+ch_status stat_setup(ch_ctx* ctx, const int32_t* members, int32_t nm, int32_t& M, double& dt, int64_t& J)
+{
+    const int m = (int)ctx->desc.size();
+    std::vector<int32_t> sel;
+    if (members) {
+        if (nm < 1) return fail(ctx, CH_EINVAL, "empty member selection");
+        sel.assign(members, members + nm);
+    } else {
+        sel.resize(m);
+        for (int i = 0; i < m; ++i) sel[i] = i;
+    }
+    for (int32_t i : sel)
+        if (i < 0 || i >= m) return fail(ctx, CH_EINVAL, "member index %d out of range", i);
+    dt = ctx->desc[sel[0]].dt;
+    for (int32_t i : sel)
+        if (ctx->desc[i].dt != dt) return fail(ctx, CH_EINVAL, "selected members have different dt");
+    M = (int32_t)sel.size();
+    J = std::min<int64_t>(ctx->step / ctx->K + 1, ctx->max_samples);
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_statm(), sel.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice,
+                               ctx->stream));
+    // the host list must outlive the copy; also the non-finite flags
+    std::vector<int32_t> flags(m);
+    HIPCHK(ctx, hipMemcpyAsync(flags.data(), ctx->d_flags(), sizeof(int32_t) * m, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int32_t i : sel)
+        if (flags[i]) return fail(ctx, CH_ENONFINITE, "non-finite free energy in member %d", i);
+    return CH_OK;
+}
+
+// first and last recorded samples with t1 <= t_j <= t2, t_j = (jK) dt
+bool window_range(const ch_ctx* ctx, double dt, int64_t J, double t1, double t2, int64_t& j0, int64_t& j1)
+{
+    j0 = -1;
+    j1 = -1;
+    for (int64_t j = 0; j < J; ++j) {
+        const double t = (double)(j * ctx->K) * dt;
+        if (t >= t1 && t <= t2) {
+            if (j0 < 0) j0 = j;
+            j1 = j;
+        }
+    }
+    return j0 >= 0;
+}
+}  // namespace
+
+ch_status ch_ensemble_moments(ch_ctx* ctx, const int32_t* members, int32_t nm, int32_t pmax, double* t,
+                              double* mu, int64_t cap, int64_t* count)
+{
+    ch_status st = check_ctx(ctx);
+    if (st != CH_OK) return st;
+    if (pmax < 1 || pmax > kMaxMoments || cap < 0 || !mu || !count)
+        return fail(ctx, CH_EINVAL, "need 1 <= pmax <= %d, cap >= 0, mu and count", kMaxMoments);
+    int32_t M;
+    double dt;
+    int64_t J;
+    if ((st = stat_setup(ctx, members, nm, M, dt, J)) != CH_OK) return st;
+    J = std::min<int64_t>(J, cap);
+    *count = J;
+    if (J == 0) return CH_OK;
+    HIPCHK(ctx, launch_moments(ctx->d_series(), ctx->max_samples, ctx->d_statm(), M, ctx->K, ctx->step, dt,
+                               pmax, ctx->d_stat(), J, ctx->stream));
+    std::vector<double> buf(kMaxMoments * (size_t)J);
+    HIPCHK(ctx, hipMemcpyAsync(buf.data(), ctx->d_stat(), sizeof(double) * buf.size(), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int64_t j = 0; j < J; ++j) {
+        if (t) t[j] = (double)(j * ctx->K) * dt;
+        for (int p = 0; p < pmax; ++p) mu[j * pmax + p] = buf[j * kMaxMoments + p];
+    }
+    return CH_OK;
+}
+
+ch_status ch_ensemble_window(ch_ctx* ctx, const int32_t* members, int32_t nm, double t1, double t2,
+                             double* beta0, double* k)
+{
+    ch_status st = check_ctx(ctx);
+    if (st != CH_OK) return st;
+    if (!(t1 <= t2)) return fail(ctx, CH_EINVAL, "need t1 <= t2");
+    int32_t M;
+    double dt;
+    int64_t J;
+    if ((st = stat_setup(ctx, members, nm, M, dt, J)) != CH_OK) return st;
+    int64_t j0, j1;
+    double out[2] = {std::nan(""), std::nan("")};
+    if (window_range(ctx, dt, J, t1, t2, j0, j1)) {
+        double* d_out = ctx->d_stat() + kMaxMoments * (size_t)ctx->max_samples;
+        HIPCHK(ctx, launch_moments(ctx->d_series(), ctx->max_samples, ctx->d_statm(), M, ctx->K, ctx->step,
+                                   dt, 2, ctx->d_stat(), J, ctx->stream));
+        HIPCHK(ctx, launch_window(ctx->d_stat(), j0, j1, ctx->K, dt, d_out, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(out, d_out, sizeof out, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    if (beta0) *beta0 = out[0];
+    if (k) *k = out[1];
+    return CH_OK;
+}
+
+ch_status ch_beta_histogram(ch_ctx* ctx, const int32_t* members, int32_t nm, double t1, double t2,
+                            double lo, double hi, int32_t nbins, uint64_t* counts)
+{
+    ch_status st = check_ctx(ctx);
+    if (st != CH_OK) return st;
+    if (!counts || nbins < 1 || nbins > kMaxHistBins || !(lo < hi) || !(t1 <= t2))
+        return fail(ctx, CH_EINVAL, "need counts, 1 <= nbins <= %d, lo < hi, t1 <= t2", kMaxHistBins);
+    int32_t M;
+    double dt;
+    int64_t J;
+    if ((st = stat_setup(ctx, members, nm, M, dt, J)) != CH_OK) return st;
+    std::vector<uint64_t> h(nbins + 2, 0);
+    int64_t j0, j1;
+    if (window_range(ctx, dt, J, t1, t2, j0, j1)) {
+        HIPCHK(ctx, launch_hist(ctx->d_series(), ctx->max_samples, ctx->d_statm(), M, ctx->K, ctx->step, dt,
+                                j0, j1, lo, hi, nbins,
+                                reinterpret_cast<unsigned long long*>(ctx->d_hist()), ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(h.data(), ctx->d_hist(), sizeof(uint64_t) * h.size(), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    std::copy(h.begin(), h.end(), counts);
     return CH_OK;
 }
 

@@ -12,6 +12,7 @@ constexpr int kWaveScanLevels = 6; // lanes of one line inside a wavefront: P <=
 constexpr int kSeriesSlots = 5;    // F(jK-1), F(jK), F(jK+1), <C>(jK), G_id(jK)
 constexpr int kPassAThreads = 256; // 4 wavefronts
 constexpr int kColMaxThreads = 512;
+constexpr int kMaxMoments = 8;     // ensemble statistics: mu_1 .. mu_8
 constexpr int kPrefetchVecs = 12;  // several-unit pass A: 16-byte vectors per lane prefetched for the next unit
 
 // Coefficients of the periodic solve (I + rho [1,-4,6,-4,1]) y = x along one
@@ -125,6 +126,15 @@ hipError_t launch_reset(int64_t* steps, int nsteps, int64_t value, int32_t* flag
 hipError_t launch_fin(const FinArgs& f, hipStream_t s);
 hipError_t launch_beta(const double* series, int64_t max_samples, int32_t member, int32_t K,
                        int64_t ncur, double dt, double* out, int64_t J, hipStream_t s);
+hipError_t launch_moments(const double* series, int64_t max_samples, const int32_t* members, int32_t nm,
+                          int32_t K, int64_t ncur, double dt, int32_t pmax, double* out, int64_t J,
+                          hipStream_t s);
+hipError_t launch_window(const double* mom, int64_t j0, int64_t j1, int32_t K, double dt, double* out,
+                         hipStream_t s);
+// zeroes counts[0 .. nbins+1] first
+hipError_t launch_hist(const double* series, int64_t max_samples, const int32_t* members, int32_t nm,
+                       int32_t K, int64_t ncur, double dt, int64_t j0, int64_t j1, double lo, double hi,
+                       int32_t nbins, unsigned long long* counts, hipStream_t s);
 
 bool passA_has(int dim, int cx, int rl, int units);  // units > 1: several units per block
 bool col_has(int prec, int cy);

@@ -1320,34 +1320,162 @@ __global__ void reset_kernel(int64_t* steps, int nsteps, int64_t value, int32_t*
 
 // Sample j (n = jK): t, F, G_fd, G_id, beta, <C>.  G_fd is the central
 // difference of the recorded F where both neighbours exist, else one-sided.
+// G_fd and beta of sample jj (step n = jj K) of one member's series: the
+// central difference of F around n, one-sided at the ends of the recorded run.
+__device__ __forceinline__ void beta_at(const double* ser, int64_t jj, int32_t K, int64_t ncur, double dt,
+                                        double& G, double& beta)
+{
+    const int64_t n = jj * K;
+    const double Fm = ser[jj * kSeriesSlots + 0], F0 = ser[jj * kSeriesSlots + 1];
+    const double Fp = ser[jj * kSeriesSlots + 2];
+    const bool hasm = n >= 1 && !isnan(Fm);
+    const bool hasp = n + 1 <= ncur && !isnan(Fp);
+    if (hasm && hasp)
+        G = (Fp - Fm) / (2.0 * dt);
+    else if (hasp)
+        G = (Fp - F0) / dt;
+    else if (hasm)
+        G = (F0 - Fm) / dt;
+    else
+        G = __builtin_nan("");
+    const double t = (double)n * dt;
+    beta = (n == 0) ? 0.0 : -t * G / F0;
+}
+
 __global__ void beta_kernel(const double* series, int64_t max_samples, int32_t member, int32_t K,
                             int64_t ncur, double dt, double* out, int64_t J)
 {
     const double* ser = series + (int64_t)member * max_samples * kSeriesSlots;
     for (int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; jj < J;
          jj += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t n = jj * K;
-        const double Fm = ser[jj * kSeriesSlots + 0], F0 = ser[jj * kSeriesSlots + 1];
-        const double Fp = ser[jj * kSeriesSlots + 2];
-        const bool hasm = n >= 1 && !isnan(Fm);
-        const bool hasp = n + 1 <= ncur && !isnan(Fp);
-        double G;
-        if (hasm && hasp)
-            G = (Fp - Fm) / (2.0 * dt);
-        else if (hasp)
-            G = (Fp - F0) / dt;
-        else if (hasm)
-            G = (F0 - Fm) / dt;
-        else
-            G = __builtin_nan("");
-        const double t = (double)n * dt;
+        double G, beta;
+        beta_at(ser, jj, K, ncur, dt, G, beta);
         double* o = out + jj * 6;
-        o[0] = t;
-        o[1] = F0;
+        o[0] = (double)(jj * K) * dt;
+        o[1] = ser[jj * kSeriesSlots + 1];
         o[2] = G;
         o[3] = ser[jj * kSeriesSlots + 4];
-        o[4] = (n == 0) ? 0.0 : -t * G / F0;
+        o[4] = beta;
         o[5] = ser[jj * kSeriesSlots + 3];
+    }
+}
+
+// --------------------------------------------------------------------------
+// ensemble statistics of beta
+// --------------------------------------------------------------------------
+constexpr int kStatThreads = 256;
+
+// fixed-order block sum of one double per thread (result valid in thread 0)
+__device__ __forceinline__ double block_sum(double v, double* sh)
+{
+    const int tid = threadIdx.x;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    __syncthreads();  // sh free from any earlier use
+    if ((tid & 63) == 0) sh[tid >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (tid == 0)
+        for (int w = 0; w < kStatThreads / 64; ++w) r += sh[w];
+    return r;
+}
+
+// One block per sample j: mu_1 = mean over the members of beta_m(t_j), then
+// mu_p = mean of (beta_m - mu_1)^p, p = 2..pmax (two passes over the members,
+// thread-strided sums in member order, then a fixed tree).  out[j][p-1].
+__global__ void __launch_bounds__(kStatThreads) moments_kernel(const double* series, int64_t max_samples,
+                                                               const int32_t* members, int32_t nm,
+                                                               int32_t K, int64_t ncur, double dt,
+                                                               int32_t pmax, double* out, int64_t J)
+{
+    __shared__ double sh[kStatThreads / 64];
+    __shared__ double mean_sh;
+    for (int64_t jj = blockIdx.x; jj < J; jj += gridDim.x) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < nm; i += kStatThreads) {
+            double G, b;
+            beta_at(series + (int64_t)members[i] * max_samples * kSeriesSlots, jj, K, ncur, dt, G, b);
+            s += b;
+        }
+        const double tot = block_sum(s, sh);
+        if (threadIdx.x == 0) mean_sh = tot / nm;
+        __syncthreads();
+        const double mu1 = mean_sh;
+        double acc[kMaxMoments];
+#pragma unroll
+        for (int p = 0; p < kMaxMoments; ++p) acc[p] = 0.0;
+        for (int i = threadIdx.x; i < nm; i += kStatThreads) {
+            double G, b;
+            beta_at(series + (int64_t)members[i] * max_samples * kSeriesSlots, jj, K, ncur, dt, G, b);
+            const double d = b - mu1;
+            double dp = d;
+#pragma unroll
+            for (int p = 1; p < kMaxMoments; ++p) {
+                dp *= d;
+                acc[p] += dp;
+            }
+        }
+        double* o = out + jj * kMaxMoments;
+        if (threadIdx.x == 0) o[0] = mu1;
+#pragma unroll
+        for (int p = 1; p < kMaxMoments; ++p) {
+            if (p >= pmax) break;  // uniform over the block
+            const double r = block_sum(acc[p], sh);
+            if (threadIdx.x == 0) o[p] = r / nm;
+        }
+        __syncthreads();  // mean_sh is rewritten for the next sample
+    }
+}
+
+// Over the samples j0..j1: beta0 = time average of mu_1 (trapezoid rule on
+// the sample grid), k = least-squares slope of mu_2 = k t through the origin.
+// One block; out = {beta0, k}.
+__global__ void __launch_bounds__(kStatThreads) window_kernel(const double* mom, int64_t j0, int64_t j1,
+                                                              int32_t K, double dt, double* out)
+{
+    __shared__ double sh[kStatThreads / 64];
+    const double step = (double)K * dt;
+    double a = 0.0, b = 0.0, c = 0.0;  // trapezoid sum, sum t mu2, sum t^2
+    for (int64_t j = j0 + threadIdx.x; j <= j1; j += kStatThreads) {
+        const double t = (double)(j * K) * dt;
+        b += t * mom[j * kMaxMoments + 1];
+        c += t * t;
+        if (j < j1) a += 0.5 * step * (mom[j * kMaxMoments] + mom[(j + 1) * kMaxMoments]);
+    }
+    const double A = block_sum(a, sh);
+    const double B = block_sum(b, sh);
+    const double Cc = block_sum(c, sh);
+    if (threadIdx.x == 0) {
+        out[0] = (j1 > j0) ? A / ((double)(j1 - j0) * step) : __builtin_nan("");
+        out[1] = (Cc > 0.0) ? B / Cc : __builtin_nan("");
+    }
+}
+
+// Histogram of beta_m(t_j) over the members and the samples j0..j1: nbins
+// equal bins on [lo, hi), counts[0] below lo, counts[nbins + 1] at or above
+// hi, NaN not counted.  Integer atomics (order-independent).
+__global__ void __launch_bounds__(kStatThreads) hist_kernel(const double* series, int64_t max_samples,
+                                                            const int32_t* members, int32_t nm, int32_t K,
+                                                            int64_t ncur, double dt, int64_t j0, int64_t j1,
+                                                            double lo, double hi, int32_t nbins,
+                                                            unsigned long long* counts)
+{
+    const int64_t total = (j1 - j0 + 1) * (int64_t)nm;
+    const double scale = nbins / (hi - lo);
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+         it += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t jj = j0 + it / nm;
+        const int i = (int)(it - (jj - j0) * nm);
+        double G, b;
+        beta_at(series + (int64_t)members[i] * max_samples * kSeriesSlots, jj, K, ncur, dt, G, b);
+        if (isnan(b)) continue;
+        int bin;
+        if (b < lo)
+            bin = 0;
+        else if (b >= hi)
+            bin = nbins + 1;
+        else
+            bin = 1 + min(nbins - 1, (int)((b - lo) * scale));
+        atomicAdd(counts + bin, 1ull);
     }
 }
 
@@ -1524,6 +1652,44 @@ hipError_t launch_beta(const double* series, int64_t max_samples, int32_t member
     const int64_t blocks = std::min<int64_t>((J + 255) / 256, 1024);
     hipLaunchKernelGGL(beta_kernel, dim3((unsigned)blocks), dim3(256), 0, s, series, max_samples,
                        member, K, ncur, dt, out, J);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const double* series, int64_t max_samples, const int32_t* members, int32_t nm,
+                          int32_t K, int64_t ncur, double dt, int32_t pmax, double* out, int64_t J,
+                          hipStream_t s)
+{
+    if (J <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>(J, 4096);
+    hipLaunchKernelGGL(moments_kernel, dim3((unsigned)blocks), dim3(kStatThreads), 0, s, series,
+                       max_samples, members, nm, K, ncur, dt, pmax, out, J);
+    return hipGetLastError();
+}
+
+hipError_t launch_window(const double* mom, int64_t j0, int64_t j1, int32_t K, double dt, double* out,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(window_kernel, dim3(1), dim3(kStatThreads), 0, s, mom, j0, j1, K, dt, out);
+    return hipGetLastError();
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int32_t n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0ull;
+}
+
+hipError_t launch_hist(const double* series, int64_t max_samples, const int32_t* members, int32_t nm,
+                       int32_t K, int64_t ncur, double dt, int64_t j0, int64_t j1, double lo, double hi,
+                       int32_t nbins, unsigned long long* counts, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_u64_kernel, dim3((nbins + 2 + 255) / 256), dim3(256), 0, s, counts, nbins + 2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t total = (j1 - j0 + 1) * (int64_t)nm;
+    if (total <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((total + kStatThreads - 1) / kStatThreads, 4096);
+    hipLaunchKernelGGL(hist_kernel, dim3((unsigned)blocks), dim3(kStatThreads), 0, s, series, max_samples,
+                       members, nm, K, ncur, dt, j0, j1, lo, hi, nbins, counts);
     return hipGetLastError();
 }
 

@@ -89,13 +89,31 @@ def _window_stats(b64, b32, t):
     return float(mean_t.mean()), float(np.abs(mean_t).max()), se, per_member
 
 
-def _paired_runs(descs, steps, cadence=10):
+def _paired_runs(descs, steps, cadence=10, window_stats=False):
     runs = {}
     for prec in (CH_F64, CH_F32_BULK):
         ens = Ensemble(descs, prec=prec, cadence=cadence, max_samples=steps // cadence + 1)
         ens.init_random()
         ens.step(steps)
         runs[prec] = np.stack([ens.beta_series(m) for m in range(len(descs))])
+        if window_stats:
+            # device-side ensemble statistics per class (C0 = 0 / C0 = 0.3):
+            # beta0 over the second half of the run, k over the whole run;
+            # they must equal the same statistics of the device's own series
+            M = len(descs)
+            t_end = runs[prec][0, -1, 0]
+            for name, sel in (("C0=0", list(range(M // 2))), ("C0=0.3", list(range(M // 2, M)))):
+                b0, _ = ens.ensemble_window(t_end / 2, t_end, members=sel)
+                _, k = ens.ensemble_window(0.0, t_end, members=sel)
+                bt = runs[prec][sel, :, 4]
+                t = runs[prec][0, :, 0]
+                W = (t >= t_end / 2)
+                m1 = bt.mean(axis=0)
+                m2 = ((bt - m1) ** 2).mean(axis=0)
+                rb0 = np.trapezoid(m1[W], t[W]) / (t[W][-1] - t[W][0])
+                rk = float((t * m2).sum() / (t * t).sum())
+                print(f"{'FP64' if prec == CH_F64 else 'FP32'} {name}: beta0 = {b0:.4f}, k = {k:.3e}")
+                assert abs(b0 - rb0) <= 1e-12 * abs(rb0) and abs(k - rk) <= 1e-12 * abs(rk)
         ens.close()
     return runs[CH_F64], runs[CH_F32_BULK]
 
@@ -143,7 +161,7 @@ def test_m1024_fp32_vs_fp64_ensemble_mean_beta():
     for m in range(1024):
         c0 = 0.0 if m < 512 else 0.3
         descs.append(workloads.make_desc((512, 512), 0.01, 1e-3, c0=c0, noise=0.05, seed=20000 + m))
-    s64, s32 = _paired_runs(descs, 10000)
+    s64, s32 = _paired_runs(descs, 10000, window_stats=True)
     t = s64[0, :, 0]
     b64, b32 = s64[:, :, 4], s32[:, :, 4]
     d_all, dmax, se, pm = _window_stats(b64, b32, t)
