@@ -76,6 +76,25 @@ def c5() -> Workload:
                     note="8 x 256^3, gamma 0.01, dt 5e-4, C0 in {0, 0.2}, noise +-0.05")
 
 
+def droplet_ic(n: int, eps: float = 1e-6, L: float = TWO_PI) -> np.ndarray:
+    """Initial field of the convergence study of Appendix A: a single droplet
+    C = eps tanh(r - pi) on the n x n vertex grid x_i = i L / n (numpy order
+    (y, x)), with r the distance from the centre of the domain.  (Measured
+    from the grid origin, the profile would jump across the periodic
+    boundary; centred, it is continuous, and the study then reproduces the
+    errors the paper tabulates.)"""
+    x = np.arange(n) * (L / n) - L / 2
+    X, Y = np.meshgrid(x, x)  # Y varies along axis 0
+    return eps * np.tanh(np.sqrt(X * X + Y * Y) - np.pi)
+
+
+def droplet_steps(n: int, T: float = 10.0, cfl: float = 0.1, L: float = TWO_PI):
+    """(nsteps, dt) of the convergence study: dt = cfl * dx rounded so that an
+    integer number of steps ends exactly at T."""
+    nsteps = int(round(T / (cfl * L / n)))
+    return nsteps, T / nsteps
+
+
 WORKLOADS = {
     "c1": c1,
     "c2": c2,
