@@ -44,7 +44,8 @@
  *    it at the end, so the caller's stream orders all work as usual.
  *  - Asynchronous device faults surface at the next synchronising call as
  *    CH_EDEVICE.  A non-finite F sets a sticky per-member flag reported as
- *    CH_ENONFINITE by ch_energy and ch_beta_series.
+ *    CH_ENONFINITE by ch_energy, ch_beta_series and the ensemble-statistics
+ *    calls.
  *  - A context is bound to one stream and is not re-entrant.
  */
 #ifndef CH_H_
