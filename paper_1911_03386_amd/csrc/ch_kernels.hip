@@ -1174,7 +1174,6 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
     T* sF0 = sE1 + bP;
     T* sF1 = sF0 + bP;
     T* sS = sF1 + bP;  // chunk sums
-    T* sM = sS + bP;   // line means
 
     __shared__ double sred[kColMaxThreads / 64][3];
     const int tid = threadIdx.x;
@@ -1201,78 +1200,118 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
 
     const AxisCoef& ac = md.ax[a.axis];
     const T a1 = (T)ac.a1, a2 = (T)ac.a2, ik = (T)ac.ikappa;
-    T M[4], W[4];
+    T W[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        M[i] = (T)ac.M[i];
-        W[i] = (T)ac.W[i];
-    }
+    for (int i = 0; i < 4; ++i) W[i] = (T)ac.W[i];
 
     // causal recursion.  The line mean m passes through the solve unchanged;
     // the recursions run on v - m (chunk end states corrected by m * E1, the
     // end state of a chunk of ones) and m is added back at the end.
+    //
+    // The chunk end states of a column are combined by a Kogge-Stone scan over
+    // its P chunks in LDS (log2 P levels, ping-pong buffers, one barrier per
+    // level) with the powers M^(2^s) of the chunk transfer matrix; the ring is
+    // closed with (I - A^n)^{-1} as in the x-solve.
     const T E10 = (T)ac.E1[0], E11 = (T)ac.E1[1];
+    T Mp[kMaxScanLevels][4];
+#pragma unroll
+    for (int l = 0; l < kMaxScanLevels; ++l)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Mp[l][i] = (T)ac.Mp[l][i];
     T e0, e1, csum = T(0);
 #pragma unroll
     for (int k = 0; k < CY; ++k) csum += v[k];
     fwd_zero(v, a1, a2, e0, e1);
+    const int me = j * a.b + c;
+    if (colok) sS[me] = csum;
+    __syncthreads();
+    // the line mean: every thread of the column sums the P chunk sums in order
+    T tot = T(0);
+    for (int q = 0; q < P; ++q) tot += sS[q * a.b + c];
+    const T m = tot * (T)ac.inv_n;
+    e0 -= m * E10;
+    e1 -= m * E11;
+    // inclusive scan S_j = f_j + M S_{j-1} over the chunks of the column
+    // ping-pong buffers (a select, not an indexed pointer array: no scratch)
+    auto B0 = [&](int q) { return q ? sF0 : sE0; };
+    auto B1 = [&](int q) { return q ? sF1 : sE1; };
+    int pp = 0;
+#pragma unroll
+    for (int l = 0; l < kMaxScanLevels; ++l) {
+        const int d = 1 << l;
+        if (d >= P) break;  // uniform
+        if (colok) {
+            B0(pp)[me] = e0;
+            B1(pp)[me] = e1;
+        }
+        __syncthreads();
+        if (colok && j >= d) {
+            T y0 = B0(pp)[me - d * a.b], y1 = B1(pp)[me - d * a.b];
+            mv(Mp[l], y0, y1);
+            e0 += y0;
+            e1 += y1;
+        }
+        pp ^= 1;
+    }
     if (colok) {
-        sE0[j * a.b + c] = e0;
-        sE1[j * a.b + c] = e1;
-        sS[j * a.b + c] = csum;
+        B0(pp)[me] = e0;
+        B1(pp)[me] = e1;
     }
     __syncthreads();
-    if (colok && j0 == 0) {
-        T tot = T(0);
-        for (int q = 0; q < P; ++q) tot += sS[q * a.b + c];
-        const T mm = tot * (T)ac.inv_n;
-        sM[c] = mm;
-        T z0 = T(0), z1 = T(0);
-        for (int q = 0; q < P; ++q) {
-            mv(M, z0, z1);
-            z0 += sE0[q * a.b + c] - mm * E10;
-            z1 += sE1[q * a.b + c] - mm * E11;
+    {
+        // state after the whole column = entering chunk 0, carried to chunk j
+        const T z0 = B0(pp)[(P - 1) * a.b + c], z1 = B1(pp)[(P - 1) * a.b + c];
+        T r0 = W[0] * z0 + W[1] * z1, r1 = W[2] * z0 + W[3] * z1;
+#pragma unroll
+        for (int l = 0; l < kMaxScanLevels; ++l)
+            if (((1 << l) < P) && (j & (1 << l))) mv(Mp[l], r0, r1);
+        if (j > 0) {
+            r0 += B0(pp)[me - a.b];
+            r1 += B1(pp)[me - a.b];
         }
-        T s0 = W[0] * z0 + W[1] * z1, s1 = W[2] * z0 + W[3] * z1;
-        for (int q = 0; q < P; ++q) {
-            const T f0 = sE0[q * a.b + c] - mm * E10, f1 = sE1[q * a.b + c] - mm * E11;
-            sE0[q * a.b + c] = s0;
-            sE1[q * a.b + c] = s1;
-            mv(M, s0, s1);
-            s0 += f0;
-            s1 += f1;
-        }
+        fwd_true(v, a1, a2, r0, r1, m);
     }
-    __syncthreads();
-    const T m = sM[c];
-    fwd_true(v, a1, a2, sE0[j * a.b + c], sE1[j * a.b + c], m);
+    __syncthreads();  // the scan buffers are reused below
 
-    // anti-causal recursion
+    // anti-causal recursion: the same scan over the reversed chunk order
     bwd_zero(v, a1, a2, e0, e1);
+    const int jr = P - 1 - j;
+    pp = 0;
+#pragma unroll
+    for (int l = 0; l < kMaxScanLevels; ++l) {
+        const int d = 1 << l;
+        if (d >= P) break;  // uniform
+        if (colok) {
+            B0(pp)[me] = e0;
+            B1(pp)[me] = e1;
+        }
+        __syncthreads();
+        if (colok && jr >= d) {
+            T y0 = B0(pp)[me + d * a.b], y1 = B1(pp)[me + d * a.b];
+            mv(Mp[l], y0, y1);
+            e0 += y0;
+            e1 += y1;
+        }
+        pp ^= 1;
+    }
     if (colok) {
-        sF0[j * a.b + c] = e0;
-        sF1[j * a.b + c] = e1;
+        B0(pp)[me] = e0;
+        B1(pp)[me] = e1;
     }
     __syncthreads();
-    if (colok && j0 == P - 1) {
-        T z0 = T(0), z1 = T(0);
-        for (int q = P - 1; q >= 0; --q) {
-            mv(M, z0, z1);
-            z0 += sF0[q * a.b + c];
-            z1 += sF1[q * a.b + c];
+    {
+        // state at the column start = entering chunk P-1 (from above), carried down
+        const T z0 = B0(pp)[c], z1 = B1(pp)[c];
+        T r0 = W[0] * z0 + W[1] * z1, r1 = W[2] * z0 + W[3] * z1;
+#pragma unroll
+        for (int l = 0; l < kMaxScanLevels; ++l)
+            if (((1 << l) < P) && (jr & (1 << l))) mv(Mp[l], r0, r1);
+        if (j < P - 1) {
+            r0 += B0(pp)[me + a.b];
+            r1 += B1(pp)[me + a.b];
         }
-        T s0 = W[0] * z0 + W[1] * z1, s1 = W[2] * z0 + W[3] * z1;
-        for (int q = P - 1; q >= 0; --q) {
-            const T f0 = sF0[q * a.b + c], f1 = sF1[q * a.b + c];
-            sF0[q * a.b + c] = s0;
-            sF1[q * a.b + c] = s1;
-            mv(M, s0, s1);
-            s0 += f0;
-            s1 += f1;
-        }
+        bwd_true(v, a1, a2, r0, r1, ik, m);
     }
-    __syncthreads();
-    bwd_true(v, a1, a2, sF0[j * a.b + c], sF1[j * a.b + c], ik, m);
 
     if (colok)
 #pragma unroll
@@ -1581,7 +1620,7 @@ hipError_t launch_passA(int prec, int dim, int cx, int rl, int units, const Pass
 template <typename T, int CY>
 static hipError_t launchC(const ColArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    const size_t lds = ((size_t)5 * a.b * a.P + a.b) * sizeof(T);
+    const size_t lds = (size_t)5 * a.b * a.P * sizeof(T);
     const int threads = (a.b * a.P + 63) / 64 * 64;
     return launch_k(col_kernel<T, CY>, (unsigned)a.nblocks, threads, lds, s, a, ev0, ev1);
 }
