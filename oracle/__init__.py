@@ -82,6 +82,8 @@ def lib():
                                      ctypes.c_int64]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_set_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -212,3 +214,8 @@ def run_series(C: np.ndarray, gamma: float, dt: float, nsteps: int, K: int = 10,
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> int:
+    """Use n OpenMP threads from now on; returns the previous count."""
+    return lib().orc_set_num_threads(n)

@@ -645,3 +645,15 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads for the following calls (n >= 1); returns the previous count. */
+int orc_set_num_threads(int n)
+{
+    const int prev = orc_num_threads();
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+    return prev;
+}
