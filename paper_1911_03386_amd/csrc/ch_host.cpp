@@ -772,6 +772,67 @@ std::string class_key(const ch_ctx* ctx, const ClassPlan& c)
     return buf;
 }
 
+// The fastest few shapes of one class key in isolation: [0] pass A
+// (cx, rl, waves, units), [1] y sweep (cy, b), [2] z sweep (cy, b).
+struct Shortlist {
+    static constexpr size_t kKeep[3] = {3, 2, 2};
+    std::vector<std::pair<float, std::vector<int>>> c[3];
+    void add(int k, float ms, std::vector<int> shape)
+    {
+        auto& v = c[k];
+        v.emplace_back(ms, std::move(shape));
+        std::sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+        if (v.size() > kKeep[k]) v.resize(kKeep[k]);
+    }
+};
+
+// Validate a member selection (NULL = all members), require a common dt, copy
+// the list to the workspace and report the recorded sample count.
+ch_status stat_setup(ch_ctx* ctx, const int32_t* members, int32_t nm, int32_t& M, double& dt, int64_t& J)
+{
+    const int m = (int)ctx->desc.size();
+    std::vector<int32_t> sel;
+    if (members) {
+        if (nm < 1) return fail(ctx, CH_EINVAL, "empty member selection");
+        sel.assign(members, members + nm);
+    } else {
+        sel.resize(m);
+        for (int i = 0; i < m; ++i) sel[i] = i;
+    }
+    for (int32_t i : sel)
+        if (i < 0 || i >= m) return fail(ctx, CH_EINVAL, "member index %d out of range", i);
+    dt = ctx->desc[sel[0]].dt;
+    for (int32_t i : sel)
+        if (ctx->desc[i].dt != dt) return fail(ctx, CH_EINVAL, "selected members have different dt");
+    M = (int32_t)sel.size();
+    J = std::min<int64_t>(ctx->step / ctx->K + 1, ctx->max_samples);
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_statm(), sel.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice,
+                               ctx->stream));
+    // the host list must outlive the copy; also the non-finite flags
+    std::vector<int32_t> flags(m);
+    HIPCHK(ctx, hipMemcpyAsync(flags.data(), ctx->d_flags(), sizeof(int32_t) * m, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int32_t i : sel)
+        if (flags[i]) return fail(ctx, CH_ENONFINITE, "non-finite free energy in member %d", i);
+    return CH_OK;
+}
+
+// first and last recorded samples with t1 <= t_j <= t2, t_j = (jK) dt
+bool window_range(const ch_ctx* ctx, double dt, int64_t J, double t1, double t2, int64_t& j0, int64_t& j1)
+{
+    j0 = -1;
+    j1 = -1;
+    for (int64_t j = 0; j < J; ++j) {
+        const double t = (double)(j * ctx->K) * dt;
+        if (t >= t1 && t <= t2) {
+            if (j0 < 0) j0 = j;
+            j1 = j;
+        }
+    }
+    return j0 >= 0;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1122,22 +1183,6 @@ ch_status ch_time_kernels(ch_ctx* ctx, int64_t nsteps, double* ms)
     return CH_OK;
 }
 
-namespace {
-// The fastest few shapes of one class key in isolation: [0] pass A
-// (cx, rl, waves, units), [1] y sweep (cy, b), [2] z sweep (cy, b).
-struct Shortlist {
-    static constexpr size_t kKeep[3] = {3, 2, 2};
-    std::vector<std::pair<float, std::vector<int>>> c[3];
-    void add(int k, float ms, std::vector<int> shape)
-    {
-        auto& v = c[k];
-        v.emplace_back(ms, std::move(shape));
-        std::sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
-        if (v.size() > kKeep[k]) v.resize(kKeep[k]);
-    }
-};
-}  // namespace
-
 ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
 {
     ch_status st = check_ctx(ctx);
@@ -1415,55 +1460,6 @@ ch_status ch_destroy(ch_ctx* ctx)
 }
 
 // ---- ensemble statistics of beta ---------------------------------------------
-
-namespace {
-// Validate a member selection (NULL = all members), require a common dt, copy
-// the list to the workspace and report the recorded sample count.
-ch_status stat_setup(ch_ctx* ctx, const int32_t* members, int32_t nm, int32_t& M, double& dt, int64_t& J)
-{
-    const int m = (int)ctx->desc.size();
-    std::vector<int32_t> sel;
-    if (members) {
-        if (nm < 1) return fail(ctx, CH_EINVAL, "empty member selection");
-        sel.assign(members, members + nm);
-    } else {
-        sel.resize(m);
-        for (int i = 0; i < m; ++i) sel[i] = i;
-    }
-    for (int32_t i : sel)
-        if (i < 0 || i >= m) return fail(ctx, CH_EINVAL, "member index %d out of range", i);
-    dt = ctx->desc[sel[0]].dt;
-    for (int32_t i : sel)
-        if (ctx->desc[i].dt != dt) return fail(ctx, CH_EINVAL, "selected members have different dt");
-    M = (int32_t)sel.size();
-    J = std::min<int64_t>(ctx->step / ctx->K + 1, ctx->max_samples);
-    HIPCHK(ctx, hipMemcpyAsync(ctx->d_statm(), sel.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice,
-                               ctx->stream));
-    // the host list must outlive the copy; also the non-finite flags
-    std::vector<int32_t> flags(m);
-    HIPCHK(ctx, hipMemcpyAsync(flags.data(), ctx->d_flags(), sizeof(int32_t) * m, hipMemcpyDeviceToHost,
-                               ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    for (int32_t i : sel)
-        if (flags[i]) return fail(ctx, CH_ENONFINITE, "non-finite free energy in member %d", i);
-    return CH_OK;
-}
-
-// first and last recorded samples with t1 <= t_j <= t2, t_j = (jK) dt
-bool window_range(const ch_ctx* ctx, double dt, int64_t J, double t1, double t2, int64_t& j0, int64_t& j1)
-{
-    j0 = -1;
-    j1 = -1;
-    for (int64_t j = 0; j < J; ++j) {
-        const double t = (double)(j * ctx->K) * dt;
-        if (t >= t1 && t <= t2) {
-            if (j0 < 0) j0 = j;
-            j1 = j;
-        }
-    }
-    return j0 >= 0;
-}
-}  // namespace
 
 ch_status ch_ensemble_moments(ch_ctx* ctx, const int32_t* members, int32_t nm, int32_t pmax, double* t,
                               double* mu, int64_t cap, int64_t* count)
