@@ -184,8 +184,13 @@ ch_status ch_set_tiles(ch_ctx* ctx, int32_t cls, int32_t cx, int32_t rl, int32_t
 /* HIP graphs: with graph_steps > 0, ch_step replays a captured graph of
  * graph_steps steps (default 16); 0 launches every kernel directly.  Kernels
  * are always launched directly on the legacy null stream (it cannot be
- * captured) and while the caller is capturing the stream itself. */
+ * captured) and while the caller is capturing the stream itself.  A graph the
+ * caller captures advances the device step counter on every replay, while the
+ * host keeps the count it had at capture: ch_sync_step reads the device
+ * counter back (synchronising the stream) so that later calls see the true
+ * step; it changes neither the state nor the series. */
 ch_status ch_set_graph_steps(ch_ctx* ctx, int32_t graph_steps);
+ch_status ch_sync_step(ch_ctx* ctx, int64_t* n);
 
 /* Describe the chosen tile shapes as text (for logs), NUL-terminated. */
 ch_status ch_describe(const ch_ctx* ctx, char* buf, size_t cap);

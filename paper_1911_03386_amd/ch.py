@@ -31,7 +31,7 @@ EXPORTED = (
     "ch_get_step", "ch_set_step", "ch_step", "ch_energy", "ch_beta_series", "ch_autotune",
     "ch_set_graph_steps", "ch_describe", "ch_time_kernels", "ch_destroy", "ch_last_error",
     "ch_version", "ch_solver_coefficients", "ch_num_classes", "ch_set_tiles",
-    "ch_ensemble_moments", "ch_ensemble_window", "ch_beta_histogram",
+    "ch_ensemble_moments", "ch_ensemble_window", "ch_beta_histogram", "ch_sync_step",
 )
 
 
@@ -95,6 +95,7 @@ def load() -> ctypes.CDLL:
                                                   ctypes.c_int32, dp]),
         "ch_num_classes": (ctypes.c_int, [vp, P(ctypes.c_int32)]),
         "ch_set_tiles": (ctypes.c_int, [vp] + [ctypes.c_int32] * 9),
+        "ch_sync_step": (ctypes.c_int, [vp, i64p]),
         "ch_ensemble_moments": (ctypes.c_int, [vp, P(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32, dp,
                                                dp, ctypes.c_int64, i64p]),
         "ch_ensemble_window": (ctypes.c_int, [vp, P(ctypes.c_int32), ctypes.c_int32, ctypes.c_double,
@@ -226,6 +227,13 @@ class Ensemble:
 
     def set_step(self, n: int):
         _check(load().ch_set_step(self.ctx, n), self.ctx)
+
+    def sync_step(self) -> int:
+        """Read the device step counter back (after replays of a graph the
+        caller captured) and return it."""
+        n = ctypes.c_int64()
+        _check(load().ch_sync_step(self.ctx, ctypes.byref(n)), self.ctx)
+        return n.value
 
     def step(self, nsteps: int):
         _check(load().ch_step(self.ctx, nsteps), self.ctx)

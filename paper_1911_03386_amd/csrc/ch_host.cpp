@@ -1043,6 +1043,20 @@ ch_status ch_set_step(ch_ctx* ctx, int64_t n)
     return CH_OK;
 }
 
+ch_status ch_sync_step(ch_ctx* ctx, int64_t* n)
+{
+    ch_status st = check_ctx(ctx);
+    if (st != CH_OK) return st;
+    int64_t dev = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&dev, ctx->d_steps(), sizeof dev, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (dev < 0 || dev / ctx->K >= ctx->max_samples)
+        return fail(ctx, CH_ESTATE, "device step counter %lld out of range", (long long)dev);
+    ctx->step = dev;
+    if (n) *n = dev;
+    return CH_OK;
+}
+
 ch_status ch_step(ch_ctx* ctx, int64_t nsteps)
 {
     ch_status st = check_ctx(ctx);

@@ -421,3 +421,43 @@ def test_autotune_split_classes(tmp_path):
         ref = oracle.step(_ref_field(d, (32, 64)), d.gamma, d.dt, N)
         assert float(np.abs(ens.get_field(m) - ref).max()) <= TOL
     ens.close()
+
+
+def test_caller_captured_graph_replays():
+    """The caller captures ch_step on the context's stream in a graph of its
+    own (the library then launches directly, forking its class streams into
+    the capture) and replays it several times, with its own eager work and
+    synchronisations between the replays.  Every replay equals the same steps
+    taken eagerly."""
+    import torch
+
+    descs = [make_desc((64, 32), 0.01, 1e-3, c0=0.05 * (m % 3), noise=0.1, seed=600 + m)
+             for m in range(16)]  # 4 classes on 4 streams
+    chunk, nrep, K = 20, 3, 10
+    ref = Ensemble(descs, prec=CH_F64, cadence=K, max_samples=chunk * (nrep + 1) // K + 1)
+    ref.set_graph_steps(0)
+    ref.init_random()
+    ens = Ensemble(descs, prec=CH_F64, cadence=K, max_samples=chunk * (nrep + 1) // K + 1)
+    assert ens.num_classes() == 4
+    ens.init_random()
+    ens.step(chunk)  # warm-up outside the capture (also builds nothing captured)
+    ref.step(chunk)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=ens.stream):
+        ens.step(chunk)
+    scratch = torch.zeros(1 << 20, device="cuda")
+    for r in range(nrep):
+        g.replay()
+        scratch.add_(1.0)  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        ref.step(chunk)
+        for m in (0, 5, 10, 15):
+            np.testing.assert_array_equal(ens.get_field(m), ref.get_field(m))
+    # the replays advanced the device step counter; the host learns it here
+    assert ens.step_count == 2 * chunk
+    assert ens.sync_step() == chunk * (nrep + 1) == ens.step_count
+    for m in (0, 15):
+        np.testing.assert_array_equal(ens.beta_series(m), ref.beta_series(m))
+    ens.close()
+    ref.close()
