@@ -147,7 +147,7 @@ def dp45(f, y0, t_end: float, dts: float, rtol: float, atol: float, h0: float,
             h = h * max(0.2, 0.9 * err ** -0.2)
             rejected_last = True
             rej += 1
-        if t + h == t:
+        if jn < J and t + h == t:
             raise FloatingPointError("step size underflow")
     return y, acc, rej
 
@@ -169,10 +169,12 @@ def mean_field(V: np.ndarray) -> float:
 
 
 def rate(V: np.ndarray) -> np.ndarray:
-    """dV/dt = 3 (ubar R - 1) for live droplets, 0 for dead ones."""
+    """dV/dt = 3 (ubar R - 1) for live droplets, 0 for dead ones, with ubar of
+    eq. (uval) (the same sum as mean_field)."""
     alive = V > 0.0
     R = np.where(alive, np.cbrt(np.where(alive, V, 1.0)), 0.0)
-    ubar = mean_field(V)
+    cnt = int(np.count_nonzero(alive))
+    ubar = cnt / float(np.sum(R[alive])) if cnt else 0.0
     return np.where(alive, 3.0 * (ubar * R - 1.0), 0.0)
 
 

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libch.so")
-SOURCES = ["ch_kernels.hip", "ch_host.cpp"]
+SOURCES = ["ch_kernels.hip", "ch_host.cpp", "dp_kernels.hip", "dp_host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -111,3 +111,27 @@ def get(name: str) -> Workload:
 
 def names() -> List[str]:
     return list(WORKLOADS)
+
+
+# ---- Model 1: droplet populations (Section 3, Table "ensembles") ------------
+# M = 100 populations for each N = 128 ... 8192, initial radii i.i.d. U(0, 1)
+# (eq. (dRi_init)), statistics over t in [0, 40].
+MODEL1_N = (128, 256, 512, 1024, 2048, 4096, 8192)
+MODEL1_M = 100
+MODEL1_T_END = 40.0
+
+
+def model1_radii(n: int, seed: int) -> np.ndarray:
+    """Initial radii of one population: n draws of U(0, 1), seeded."""
+    return np.random.default_rng(seed).uniform(0.0, 1.0, n)
+
+
+def model1_ensemble(ns=MODEL1_N, M: int = MODEL1_M, base_seed: int = 7000):
+    """(sizes, radii) of M populations per size in ns; member m of size index
+    k uses seed base_seed + 1000 k + m."""
+    sizes, radii = [], []
+    for k, n in enumerate(ns):
+        for m in range(M):
+            sizes.append(int(n))
+            radii.append(model1_radii(int(n), base_seed + 1000 * k + m))
+    return sizes, radii

@@ -181,3 +181,48 @@ def test_factorised_solve_fp32_coefficients():
     # DC gain is exactly one for the rounded coefficients (up to FP64 rounding)
     a1, a2, ik = coef[:3]
     assert abs(ik / (1 - a1 - a2) ** 2 - 1) < 1e-15
+
+
+# ---- droplet-population ensembles (include/dp.h) -----------------------------
+
+DP_HEADER = os.path.join(os.path.dirname(HEADER), "dp.h")
+
+
+def test_library_exports_every_droplet_symbol():
+    from paper_1911_03386_amd import dp
+
+    text = re.sub(r"/\*.*?\*/", "", open(DP_HEADER).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(dp_[a-z_0-9]+)\s*\(", text)))
+    assert len(names) >= 12
+    lib = dp.lib()
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(dp.EXPORTED)
+
+
+@pytest.mark.parametrize("n,kw,frag", [
+    ([0], {}, "1 <= n"),
+    ([8193], {}, "1 <= n"),
+    ([16], dict(dt_sample=0.0), "dt_sample > 0"),
+    ([16], dict(rtol=-1.0), "rtol > 0"),
+    ([16], dict(t_end=float("inf")), "t_end >= 0"),
+    ([16], dict(max_attempts=0), "max_attempts"),
+])
+def test_droplet_workspace_rejects(n, kw, frag):
+    from paper_1911_03386_amd import dp
+
+    args = dict(t_end=1.0)
+    args.update(kw)
+    with pytest.raises(dp.DpError) as e:
+        dp.workspace_bytes(n, dp.make_params(**args))
+    assert frag in str(e.value)
+
+
+def test_droplet_workspace_grows_with_samples_and_droplets():
+    from paper_1911_03386_amd import dp
+
+    a = dp.workspace_bytes([128, 8192], dp.make_params(40.0, 0.1))
+    b = dp.workspace_bytes([128, 8192], dp.make_params(80.0, 0.1))
+    c = dp.workspace_bytes([128, 8192, 8192], dp.make_params(40.0, 0.1))
+    assert 0 < a < b and a < c
+    assert a >= 8 * (128 + 8192) + 8 * 6 * 2 * 401
