@@ -33,8 +33,8 @@ constexpr int64_t kMaxSamples = int64_t(1) << 24;
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t off_mem = 0, off_order = 0, off_state = 0, off_V = 0, off_series = 0, off_statm = 0, off_stat = 0,
-           off_hist = 0, total = 0;
+    size_t off_mem = 0, off_order = 0, off_state = 0, off_V = 0, off_slot = 0, off_series = 0, off_statm = 0,
+           off_stat = 0, off_hist = 0, total = 0;
 };
 
 Layout layout(int32_t m, int64_t total_n, int64_t J)
@@ -49,6 +49,8 @@ Layout layout(int32_t m, int64_t total_n, int64_t J)
     o = align_up(o + sizeof(dp::State) * (size_t)m);
     L.off_V = o;
     o = align_up(o + sizeof(double) * (size_t)total_n);
+    L.off_slot = o;
+    o = align_up(o + sizeof(int32_t) * (size_t)total_n);
     L.off_series = o;
     o = align_up(o + sizeof(double) * kSlots * (size_t)m * (size_t)J);
     L.off_statm = o;
@@ -117,6 +119,7 @@ struct dp_ctx {
     int32_t* d_order() { return reinterpret_cast<int32_t*>(ws + L.off_order); }
     dp::State* d_state() { return reinterpret_cast<dp::State*>(ws + L.off_state); }
     double* d_V() { return reinterpret_cast<double*>(ws + L.off_V); }
+    int32_t* d_slot() { return reinterpret_cast<int32_t*>(ws + L.off_slot); }
     double* d_series() { return reinterpret_cast<double*>(ws + L.off_series); }
     int32_t* d_statm() { return reinterpret_cast<int32_t*>(ws + L.off_statm); }
     double* d_stat() { return reinterpret_cast<double*>(ws + L.off_stat); }
@@ -129,6 +132,7 @@ struct dp_ctx {
         a.order = d_order();
         a.st = d_state();
         a.V = d_V();
+        a.slot = d_slot();
         a.series = d_series();
         a.J = J;
         a.dts = prm.dt_sample;

@@ -34,7 +34,8 @@ struct State {
     int64_t acc, rej;    // accepted and rejected step attempts
     int32_t rej_last;    // the last attempt was rejected
     int32_t status;      // MemberStatus
-    int64_t pad;
+    int32_t nslot;       // slots in use: slot j < nslot holds droplet slot[j]
+    int32_t pad;
 };
 
 struct Args {
@@ -42,6 +43,7 @@ struct Args {
     const int32_t* order;   // block b integrates member order[b]
     State* st;
     double* V;              // volumes, all members concatenated
+    int32_t* slot;          // per member (offset Member::off): droplet held by each slot
     double* series;         // [member][J][kSlots]
     int64_t J;              // samples per member: t_j = j dts
     double dts, rtol, atol, h0;

@@ -8,10 +8,15 @@
 // adaptive error control.  Every droplet's stage value depends on the other
 // droplets only through the stage's mean field, a scalar: each stage is an
 // elementwise pass over the member's droplets plus one block reduction of
-// (live count, sum of radii).  Thread tid holds droplets p*T + tid,
+// (live count, sum of radii).  Thread tid holds slots p*T + tid,
 // p = 0..P-1: their stage increments live in registers, the state V and the
 // error accumulator in LDS (private slots, so no barriers), and the
-// integrator's scalars are uniform over the block.
+// integrator's scalars are uniform over the block.  Slots hold the live
+// droplets in their original order: when deaths free a whole row of T slots,
+// the live droplets are packed to the front (the dead ones' final volumes go
+// back to global memory), so the work per stage follows the live count.  The
+// slot -> droplet map is kept in global memory, so the layout, and with it
+// every rounding, does not depend on how the run is split into launches.
 //
 // Error control, identical for every member:
 //   err = max_i |h sum_s e_s k_{s,i}| / (atol + rtol max(|V_i|, |V_i^new|)),
@@ -162,6 +167,7 @@ __global__ void __launch_bounds__(T) init_kernel(Args a)
     rd.sum2(cnt, sr);
     const double ubar = mean_field(cnt, sr);
     record<T, P>(rd, r, pm, ubar, cnt, 0.0, a.series + (int64_t)mi * a.J * kSlots);
+    for (int i = threadIdx.x; i < mb.n; i += T) a.slot[mb.off + i] = i;
     if (threadIdx.x == 0) {
         State s{};
         s.t = 0.0;
@@ -169,8 +175,65 @@ __global__ void __launch_bounds__(T) init_kernel(Args a)
         s.ubar = ubar;
         s.jn = 1;
         s.status = (a.J <= 1) ? kDone : kRunning;
+        s.nslot = mb.n;
         a.st[mi] = s;
     }
+}
+
+// Pack the live droplets (V > 0) of slots [0, nslot) to slots [0, live) in
+// slot order; dead droplets' volumes are final and go back to V.  Ranks come
+// from wave ballots: slot p*T + tid precedes every slot of a later row p and,
+// within row p, the slots of lower threads.  The old values are staged in
+// `stage` (LDS) and the droplet indices in registers, so that every old slot
+// is read before the barrier and written only after it.  Slots from
+// live_total on are cleared (V = 0: no droplet).
+template <int T, int P>
+__device__ __noinline__ void compact(double* yl, double* stage, int32_t* slot, double* V, int pm, int32_t nslot,
+                                     int32_t live_total, int32_t (*wcnt)[T / 64])
+{
+    constexpr int W = T / 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    unsigned live = 0u;
+    int32_t g[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int j = p * T + tid;
+        const bool in = p < pm && j < nslot;
+        const bool lv = in && yl[j] > 0.0;
+        live |= (lv ? 1u : 0u) << p;
+        const unsigned long long mask = __ballot(lv);
+        if (lane == 0 && p < pm) wcnt[p][w] = __popcll(mask);
+        g[p] = in ? slot[j] : -1;
+        if (in) stage[j] = yl[j];
+    }
+    __syncthreads();
+    int base = 0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        if (p < pm) {
+            const int j = p * T + tid;
+            const bool lv = (live >> p) & 1u;
+            const unsigned long long mask = __ballot(lv);
+            int inrow = 0, row = 0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                row += wcnt[p][q];
+                if (q < w) inrow += wcnt[p][q];
+            }
+            if (lv) {
+                const int d = base + inrow + __popcll(mask & below);
+                yl[d] = stage[j];
+                slot[d] = g[p];
+            } else if (g[p] >= 0) {
+                V[g[p]] = stage[j];
+            }
+            // slots past the live ones are no droplet's (no live droplet lands there)
+            if (j >= live_total) yl[j] = 0.0;
+            base += row;
+        }
+    }
+    __syncthreads();
 }
 
 // Up to `attempts` step attempts of one member per block; the state goes back
@@ -181,6 +244,7 @@ __global__ void __launch_bounds__(T) step_kernel(Args a, int64_t attempts)
 {
     extern __shared__ double lds[];
     __shared__ double red[2][2][T / 64];
+    __shared__ int32_t wcnt[P][T / 64];
     Reducer<T> rd{red};
     double* yl = lds;           // V, slot p*T + tid
     double* el = lds + P * T;   // sum_s e_s k_s
@@ -189,12 +253,13 @@ __global__ void __launch_bounds__(T) step_kernel(Args a, int64_t attempts)
     const Member mb = a.mem[mi];
     State st = a.st[mi];
     if (st.status != kRunning) return;  // uniform
-    const int pm = (mb.n + T - 1) / T;
+    int pm = (st.nslot + T - 1) / T;  // rows in use (uniform)
     double* V = a.V + mb.off;
+    int32_t* slot = a.slot + mb.off;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const int i = p * T + tid;
-        if (p < pm) yl[p * T + tid] = i < mb.n ? V[i] : 0.0;
+        const int j = p * T + tid;
+        if (p < pm) yl[j] = j < st.nslot ? V[slot[j]] : 0.0;
     }
     double* ser = a.series + (int64_t)mi * a.J * kSlots;
 
@@ -270,6 +335,12 @@ __global__ void __launch_bounds__(T) step_kernel(Args a, int64_t attempts)
                 st.jn += 1;
                 if (st.jn >= a.J) st.status = kDone;
             }
+            const int live = (int)cnt;
+            if ((live + T - 1) / T < pm) {
+                compact<T, P>(yl, el, slot, V, pm, st.nslot, live, wcnt);
+                st.nslot = live;
+                pm = (live + T - 1) / T;
+            }
         } else {
             st.h = h * fmax(0.2, 0.9 * pow(err, -0.2));
             st.rej_last = 1;
@@ -280,8 +351,8 @@ __global__ void __launch_bounds__(T) step_kernel(Args a, int64_t attempts)
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const int i = p * T + tid;
-        if (p < pm && i < mb.n) V[i] = yl[p * T + tid];
+        const int j = p * T + tid;
+        if (p < pm && j < st.nslot) V[slot[j]] = yl[j];
     }
     if (tid == 0) a.st[mi] = st;
 }
