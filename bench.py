@@ -11,6 +11,12 @@ Prints ONE JSON line.  Default workload: the FP32-bulk batched ensemble of
 64 x 512^2 grids; the same line carries the plain FP64 single 1024^2 grid
 measured the same way ("compare"), the roofline figures of the dominant
 kernel and the oracle timed on the host cores.
+
+`--workload model1` measures the droplet-population ensembles instead (Model 1
+of the paper): the whole table of Section 3 (100 populations for each N =
+128 ... 8192, t in [0, 40]) integrated in one run, as live-droplet stage
+evaluations per second, with the ensemble statistics of each N beside the
+paper's values.
 """
 from __future__ import annotations
 
@@ -25,6 +31,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
+PEAK_FP64_VECTOR_TFLOPS = 78.6  # MI355X FP64 vector, published
+# Algorithmic FP64 operations of one live-droplet stage evaluation of the
+# Dormand-Prince pair on dV/dt = 3 (ubar R - 1), the cube root not counted:
+# stage value y + h sum_j a_sj k_j (4.3 multiply-adds on average over the six
+# new stages), rate 3 (ubar R - 1) (3), mean-field sums (2), error sum (2),
+# share of the error norm (~1).
+DP_FLOPS_PER_EVAL = 17.0
+# Table of the paper's Model 1 statistics (Section 3): N -> (beta0 over
+# [20, 40], k of mu_2 = k t over [0, 40]).
+MODEL1_PAPER = {512: (0.24, 0.0075), 1024: (0.2613, 0.0036), 2048: (0.2833, 0.0017), 4096: (0.2908, 8.6e-4),
+                8192: (0.2995, 4.5e-4)}
 
 
 def parse():
@@ -43,6 +60,9 @@ def parse():
                    help="keep the default tile shapes (autotuning reads the cache first)")
     p.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1911_03386_amd", "tune_cache.txt"))
     p.add_argument("--graph-steps", type=int, default=64, help="steps per captured HIP graph")
+    p.add_argument("--dp-attempts", type=int, default=4096, help="model1: step attempts per launch")
+    p.add_argument("--dp-cpu-t-end", type=float, default=1.0,
+                   help="model1: simulated time of the oracle sample (one N = 2048 population)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of known size (for HBM counter calibration)")
     return p.parse_args()
@@ -153,6 +173,99 @@ def cpu_baseline(wl, seconds):
     }
 
 
+def bench_model1(args):
+    """The Model 1 table of Section 3 on the GPU; see the module docstring."""
+    import numpy as np
+    import torch
+
+    from paper_1911_03386_amd import workloads as W
+    from paper_1911_03386_amd.dp import DropletEnsemble
+
+    sizes, radii = W.model1_ensemble()
+    warm = 1 if args.warmup > 0 else 0
+    for _ in range(warm):
+        # the same kernels (16 droplets per thread) on a short run
+        e = DropletEnsemble([8192, 128], t_end=1e-3, dt_sample=1e-3)
+        e.set_radii([radii[-1], radii[0]])
+        e.run(args.dp_attempts)
+        e.close()
+    ens = DropletEnsemble(sizes, t_end=W.MODEL1_T_END, dt_sample=0.1)
+    ens.set_radii(radii)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    launches, kernel_ms = ens.run(args.dp_attempts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    infos = [ens.info(m) for m in range(len(sizes))]
+    evals = float(sum(i["evals"] for i in infos))
+    attempts = int(sum(i["accepted"] + i["rejected"] for i in infos))
+    stats = {}
+    for n in W.MODEL1_N:
+        idx = [m for m, v in enumerate(sizes) if v == n]
+        b0, _ = ens.ensemble_window(20.0, 40.0, idx)
+        _, k = ens.ensemble_window(0.0, 40.0, idx)
+        a = [infos[m]["accepted"] + infos[m]["rejected"] for m in idx]
+        stats[str(n)] = {"beta0": round(b0, 4), "k": float(f"{k:.3g}"), "paper": MODEL1_PAPER.get(n),
+                         "attempts_per_member": int(np.mean(a))}
+    ens.close()
+    value = evals / wall / 1e9
+    achieved = DP_FLOPS_PER_EVAL * evals / (kernel_ms / 1e3) / 1e12
+    out = {
+        "metric": "live-droplet stage evaluations/s, Model 1 table (7 x 100 populations, t <= 40)",
+        "value": round(value, 3),
+        "unit": "GEval/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": warm,
+        "ms_per_step": wall * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded U(0,1) initial radii)",
+        "config": {"workload": "model1_table", "populations": len(sizes), "sizes": list(W.MODEL1_N),
+                   "members_per_size": W.MODEL1_M, "t_end": W.MODEL1_T_END, "dt_sample": 0.1,
+                   "rtol": 1e-6, "atol": 1e-9, "attempts": attempts, "evals": evals,
+                   "time_to_solution_s": round(wall, 3)},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "dp step_kernel",
+            "achieved": round(achieved, 3),
+            "peak": PEAK_FP64_VECTOR_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP64_VECTOR_TFLOPS, 4),
+            "traffic": None,
+            "flops_per_eval": DP_FLOPS_PER_EVAL,
+            "launches": launches,
+            "ms_per_launch": round(kernel_ms / max(1, launches), 3),
+        },
+        "statistics": stats,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_model1(radii[sizes.index(2048)], args.dp_cpu_t_end)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_model1(R0, t_end):
+    """The oracle (numpy, one thread) on one N = 2048 population from t = 0."""
+    import numpy as np
+
+    from oracle import droplets as orc
+
+    live = [0]
+
+    def counting_rate(V):
+        live[0] += int(np.count_nonzero(V > 0.0))
+        return orc.rate(V)
+
+    t0 = time.perf_counter()
+    orc.dp45(counting_rate, orc.volumes_from_radii(R0), t_end, 0.1, 1e-6, 1e-9, 1e-4)
+    dt = time.perf_counter() - t0
+    evals = live[0] * 6.0 / 7.0  # the oracle evaluates all seven stages per attempt
+    return {"value": round(evals / dt / 1e9, 6), "unit": "GEval/s", "cores": 1, "kind": "oracle",
+            "sample": f"one N=2048 population of the table, t in [0, {t_end}] ({dt:.1f} s)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -161,6 +274,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "model1":
+        bench_model1(args)
         return
     from paper_1911_03386_amd import CH_F32_BULK, workloads
 

@@ -97,9 +97,12 @@ ch_status dp_advance(dp_ctx* ctx, int64_t attempts);
 ch_status dp_run(dp_ctx* ctx, int64_t attempts, int64_t* launches, double* kernel_ms);
 
 /* Progress of one member (synchronises): time reached, accepted and
- * rejected attempts, state (DP_*), samples recorded. */
+ * rejected attempts, state (DP_*), samples recorded, and the live-droplet
+ * stage evaluations so far (each attempt evaluates six new stages of every
+ * droplet alive at its start: the pair's last stage is the next step's
+ * first).  Every output pointer may be NULL. */
 ch_status dp_member_info(dp_ctx* ctx, int32_t member, double* t, int64_t* accepted, int64_t* rejected,
-                         int32_t* state, int64_t* samples);
+                         int32_t* state, int64_t* samples, double* evals);
 
 /* Current volumes of one member (n values, host memory; synchronises). */
 ch_status dp_get_volumes(dp_ctx* ctx, int32_t member, double* host_dst);

@@ -379,7 +379,7 @@ ch_status dp_run(dp_ctx* ctx, int64_t attempts, int64_t* launches, double* kerne
 }
 
 ch_status dp_member_info(dp_ctx* ctx, int32_t member, double* t, int64_t* accepted, int64_t* rejected,
-                         int32_t* state, int64_t* samples)
+                         int32_t* state, int64_t* samples, double* evals)
 {
     ch_status st = check_ctx(ctx);
     if (st != CH_OK) return st;
@@ -393,6 +393,7 @@ ch_status dp_member_info(dp_ctx* ctx, int32_t member, double* t, int64_t* accept
     if (rejected) *rejected = s.rej;
     if (state) *state = s.status;
     if (samples) *samples = s.jn;
+    if (evals) *evals = s.evals;
     return CH_OK;
 }
 

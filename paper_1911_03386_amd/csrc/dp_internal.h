@@ -27,7 +27,7 @@ struct Member {
     int32_t pad;
 };
 
-// Integrator state of one member between launches (64 bytes).
+// Integrator state of one member between launches.
 struct State {
     double t, h, ubar;   // time, next trial step, mean field of the state
     int64_t jn;          // next sample index
@@ -35,7 +35,8 @@ struct State {
     int32_t rej_last;    // the last attempt was rejected
     int32_t status;      // MemberStatus
     int32_t nslot;       // slots in use: slot j < nslot holds droplet slot[j]
-    int32_t pad;
+    int32_t live;        // live droplets of the state
+    double evals;        // live-droplet stage evaluations so far (6 per live droplet and attempt)
 };
 
 struct Args {

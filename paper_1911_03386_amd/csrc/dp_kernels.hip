@@ -176,6 +176,7 @@ __global__ void __launch_bounds__(T) init_kernel(Args a)
         s.jn = 1;
         s.status = (a.J <= 1) ? kDone : kRunning;
         s.nslot = mb.n;
+        s.live = (int32_t)cnt;
         a.st[mi] = s;
     }
 }
@@ -262,21 +263,25 @@ __global__ void __launch_bounds__(T) step_kernel(Args a, int64_t attempts)
         if (p < pm) yl[j] = j < st.nslot ? V[slot[j]] : 0.0;
     }
     double* ser = a.series + (int64_t)mi * a.J * kSlots;
+    double r[P];          // radii of the current stage's values
+    bool fresh = false;   // r holds the radii of the state (after an accepted step)
 
     for (int64_t it = 0; it < attempts; ++it) {
         if (st.acc + st.rej >= a.max_total) {
             st.status = kAttemptLimit;
             break;
         }
+        st.evals += 6.0 * st.live;  // first same as last: six new stages per attempt
         const double t_next = (double)st.jn * a.dts;
         const bool land = st.h >= t_next - st.t;
         const double h = land ? t_next - st.t : st.h;
 
         double S[6][P];  // S[s-1] = sum_{j<s} a[s][j] k_j, the increment of stage s
-        double r[P];     // radii of the current stage's values
         double ub = st.ubar, cnt = 0.0;
+        if (!fresh) {
 #pragma unroll
-        for (int p = 0; p < P; ++p) r[p] = p < pm ? radius(yl[p * T + tid]) : 0.0;
+            for (int p = 0; p < P; ++p) r[p] = p < pm ? radius(yl[p * T + tid]) : 0.0;
+        }
         double errmax = 0.0;
 #pragma unroll
         for (int s = 0; s < 7; ++s) {
@@ -335,16 +340,22 @@ __global__ void __launch_bounds__(T) step_kernel(Args a, int64_t attempts)
                 st.jn += 1;
                 if (st.jn >= a.J) st.status = kDone;
             }
+            // the last stage was evaluated at the new state: its radii are the
+            // next attempt's first-stage radii (first same as last)
+            fresh = true;
             const int live = (int)cnt;
+            st.live = live;
             if ((live + T - 1) / T < pm) {
                 compact<T, P>(yl, el, slot, V, pm, st.nslot, live, wcnt);
                 st.nslot = live;
                 pm = (live + T - 1) / T;
+                fresh = false;
             }
         } else {
             st.h = h * fmax(0.2, 0.9 * pow(err, -0.2));
             st.rej_last = 1;
             st.rej += 1;
+            fresh = false;
         }
         if (st.status == kRunning && st.t + st.h == st.t) st.status = kUnderflow;
         if (st.status != kRunning) break;

@@ -58,7 +58,7 @@ def lib() -> ctypes.CDLL:
         "dp_set_radii": (ctypes.c_int, [vp, dp_]),
         "dp_advance": (ctypes.c_int, [vp, ctypes.c_int64]),
         "dp_run": (ctypes.c_int, [vp, ctypes.c_int64, i64p, dp_]),
-        "dp_member_info": (ctypes.c_int, [vp, ctypes.c_int32, dp_, i64p, i64p, i32p, i64p]),
+        "dp_member_info": (ctypes.c_int, [vp, ctypes.c_int32, dp_, i64p, i64p, i32p, i64p, dp_]),
         "dp_get_volumes": (ctypes.c_int, [vp, ctypes.c_int32, dp_]),
         "dp_series": (ctypes.c_int, [vp, ctypes.c_int32, dp_, ctypes.c_int64, i64p]),
         "dp_ensemble_moments": (ctypes.c_int, [vp, i32p, ctypes.c_int32, ctypes.c_int32, dp_, dp_,
@@ -155,12 +155,13 @@ class DropletEnsemble:
         return nl.value, ms.value
 
     def info(self, member: int) -> dict:
-        t = ctypes.c_double()
+        t, evals = ctypes.c_double(), ctypes.c_double()
         acc, rej, samples = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         state = ctypes.c_int32()
         _check(lib().dp_member_info(self.ctx, member, ctypes.byref(t), ctypes.byref(acc), ctypes.byref(rej),
-                                    ctypes.byref(state), ctypes.byref(samples)), self.ctx)
-        return dict(t=t.value, accepted=acc.value, rejected=rej.value, state=state.value, samples=samples.value)
+                                    ctypes.byref(state), ctypes.byref(samples), ctypes.byref(evals)), self.ctx)
+        return dict(t=t.value, accepted=acc.value, rejected=rej.value, state=state.value, samples=samples.value,
+                    evals=evals.value)
 
     def volumes(self, member: int) -> np.ndarray:
         out = np.empty(self.n[member])
