@@ -61,6 +61,7 @@ def parse():
     p.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1911_03386_amd", "tune_cache.txt"))
     p.add_argument("--graph-steps", type=int, default=64, help="steps per captured HIP graph")
     p.add_argument("--dp-attempts", type=int, default=4096, help="model1: step attempts per launch")
+    p.add_argument("--model1-ns", default="", help="model1: only these population sizes (comma-separated)")
     p.add_argument("--dp-cpu-t-end", type=float, default=1.0,
                    help="model1: simulated time of the oracle sample (one N = 2048 population)")
     p.add_argument("--copy-calibration", action="store_true",
@@ -181,12 +182,13 @@ def bench_model1(args):
     from paper_1911_03386_amd import workloads as W
     from paper_1911_03386_amd.dp import DropletEnsemble
 
-    sizes, radii = W.model1_ensemble()
+    ns = tuple(int(v) for v in args.model1_ns.split(",")) if args.model1_ns else W.MODEL1_N
+    sizes, radii = W.model1_ensemble(ns=ns)
     warm = 1 if args.warmup > 0 else 0
     for _ in range(warm):
         # the same kernels (16 droplets per thread) on a short run
         e = DropletEnsemble([8192, 128], t_end=1e-3, dt_sample=1e-3)
-        e.set_radii([radii[-1], radii[0]])
+        e.set_radii([W.model1_radii(8192, 1), W.model1_radii(128, 2)])
         e.run(args.dp_attempts)
         e.close()
     ens = DropletEnsemble(sizes, t_end=W.MODEL1_T_END, dt_sample=0.1)
@@ -200,7 +202,7 @@ def bench_model1(args):
     evals = float(sum(i["evals"] for i in infos))
     attempts = int(sum(i["accepted"] + i["rejected"] for i in infos))
     stats = {}
-    for n in W.MODEL1_N:
+    for n in ns:
         idx = [m for m, v in enumerate(sizes) if v == n]
         b0, _ = ens.ensemble_window(20.0, 40.0, idx)
         _, k = ens.ensemble_window(0.0, 40.0, idx)
@@ -223,7 +225,8 @@ def bench_model1(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded U(0,1) initial radii)",
-        "config": {"workload": "model1_table", "populations": len(sizes), "sizes": list(W.MODEL1_N),
+        "config": {"workload": "model1_table" if ns == W.MODEL1_N else "model1_" + "_".join(map(str, ns)),
+                   "populations": len(sizes), "sizes": list(ns),
                    "members_per_size": W.MODEL1_M, "t_end": W.MODEL1_T_END, "dt_sample": 0.1,
                    "rtol": 1e-6, "atol": 1e-9, "attempts": attempts, "evals": evals,
                    "time_to_solution_s": round(wall, 3)},
@@ -242,7 +245,8 @@ def bench_model1(args):
         "statistics": stats,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_model1(radii[sizes.index(2048)], args.dp_cpu_t_end)
+        R0 = W.model1_ensemble(ns=(2048,), M=1)[1][0]
+        out["cpu_baseline"] = cpu_baseline_model1(R0, args.dp_cpu_t_end)
     print(json.dumps(out), flush=True)
 
 
