@@ -274,7 +274,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "ensemble members shard across GPUs without communication, see DESIGN.md", file=sys.stderr)
+              "ensemble members would shard across GPUs without communication", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
