@@ -4,6 +4,9 @@ initial radii U(0, 1), t in [0, 40]; beta0 is the time average of mu_1 over
 [20, 40] (eq. (beta0_stats)) and k the least-squares slope of mu_2 = k t over
 [0, 40].
 
+The same full-size run is checked for invariants in every population and,
+for one population of N = 512 and one of N = 1024, against the oracle.
+
 The paper's values come from its own random draws, so the comparison is
 statistical: the standard errors are bootstrap estimates over the members
 (resampling populations with replacement, statistics recomputed with the
@@ -62,6 +65,16 @@ def table_run():
     ens.run()
     rng = np.random.default_rng(0)
     out = {}
+    # invariants of every population at full size, and two sampled populations for the oracle
+    full = []
+    for m in range(len(sizes)):
+        ser, V, info = ens.series(m), ens.volumes(m), ens.info(m)
+        V0 = (radii[m] * radii[m]) * radii[m]
+        full.append((info["state"], abs(V.sum() - V0.sum()) / V0.sum(), np.all(np.diff(ser[:, 1]) <= 0.0),
+                     np.all(ser[1:, 3] >= 0.0), np.all(np.diff(ser[:, 5]) <= 0.0)))
+    out["invariants"] = full
+    out["sampled"] = {n: (ens.series(sizes.index(n)), ens.volumes(sizes.index(n)), ens.info(sizes.index(n)),
+                          radii[sizes.index(n)]) for n in (512, 1024)}
     for n in ns:
         idx = [m for m, v in enumerate(sizes) if v == n]
         b0_gpu, _ = ens.ensemble_window(20.0, 40.0, idx)
@@ -78,6 +91,23 @@ def table_run():
               f"k {k:.3g} +- {se_k:.2g} (paper {table[n][1]})")
     ens.close()
     return out
+
+
+def test_full_size_invariants(table_run):
+    # every population finished; sum V conserved (rounding); F non-increasing,
+    # beta >= 0 and the live count non-increasing at every sample
+    for m, (state, dv, f_mono, b_pos, live_mono) in enumerate(table_run["invariants"]):
+        assert state == 1 and dv < 1e-12 and f_mono and b_pos and live_mono, m
+
+
+@pytest.mark.parametrize("n", [512, 1024])
+def test_full_size_sampled_parity(table_run, n):
+    # one population of the full-size run (16 droplets per thread, as the
+    # benchmark launches it) against the oracle, with the default-tolerance bars
+    from tests.test_gpu_droplets import DEFAULT, _compare
+
+    ser, V, info, R0 = table_run["sampled"][n]
+    _compare((ser, V, info), R0, W.MODEL1_T_END, 0.1, **DEFAULT)
 
 
 @pytest.mark.parametrize("n", [512, 1024, 2048, 4096, 8192])
