@@ -11,7 +11,7 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-from .ch import CH_OK, STATUS_NAMES, load
+from .ch import CH_EINVAL, CH_ESTATE, CH_OK, STATUS_NAMES, load  # noqa: F401  (status codes re-exported)
 
 EXPORTED = (
     "dp_workspace_bytes", "dp_create", "dp_set_radii", "dp_advance", "dp_run", "dp_member_info",

@@ -226,3 +226,26 @@ def test_droplet_workspace_grows_with_samples_and_droplets():
     c = dp.workspace_bytes([128, 8192, 8192], dp.make_params(40.0, 0.1))
     assert 0 < a < b and a < c
     assert a >= 8 * (128 + 8192) + 8 * 6 * 2 * 401
+
+
+def test_droplet_create_rejects_bad_workspace_before_any_device_call():
+    import ctypes
+
+    from paper_1911_03386_amd import dp
+
+    L = dp.lib()
+    prm = dp.make_params(1.0)
+    n, p = dp._i32([64, 100])
+    nb = dp.workspace_bytes([64, 100], prm)
+    ctx = ctypes.c_void_p()
+    st = L.dp_create(p, 2, ctypes.byref(prm), None, nb, None, ctypes.byref(ctx))
+    assert st == dp.CH_EINVAL and "256-byte aligned" in dp.last_error()
+    st = L.dp_create(p, 2, ctypes.byref(prm), ctypes.c_void_p(4096 + 8), nb, None, ctypes.byref(ctx))
+    assert st == dp.CH_EINVAL and "256-byte aligned" in dp.last_error()
+    st = L.dp_create(p, 2, ctypes.byref(prm), ctypes.c_void_p(4096), nb - 1, None, ctypes.byref(ctx))
+    assert st == dp.CH_EINVAL and "need" in dp.last_error()
+    assert ctx.value is None
+    # calls on a context that does not exist are refused without touching it
+    bogus = ctypes.c_void_p(0x1000)
+    assert L.dp_advance(bogus, 1) == dp.CH_ESTATE
+    assert L.dp_destroy(None) == dp.CH_EINVAL
