@@ -46,23 +46,50 @@ constexpr double kA[7][6] = {
 constexpr double kE[7] = {71.0 / 57600.0,  0.0,          -71.0 / 16695.0, 71.0 / 1920.0,
                           -17253.0 / 339200.0, 22.0 / 525.0, -1.0 / 40.0};
 
+// Lane exchange within rows of 16 lanes by DPP (a register move, no LDS
+// round trip), on the two 32-bit halves of a double.  The patterns used are
+// involutions: quad_perm [1,0,3,2] (0xB1) and [2,3,0,1] (0x4E), half-row
+// mirror (0x141) and row mirror (0x140).
+template <int CTRL>
+__device__ __forceinline__ double dpp_swap(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Wave sum, the same bits on every lane: a butterfly within each row of 16
+// (each step adds the same two values on both lanes of a pair), then the
+// four row sums in fixed order.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_swap<0xB1>(v);
+    v += dpp_swap<0x4E>(v);
+    v += dpp_swap<0x141>(v);
+    v += dpp_swap<0x140>(v);
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 __device__ __forceinline__ double wave_max(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
+    v = fmax(v, dpp_swap<0xB1>(v));
+    v = fmax(v, dpp_swap<0x4E>(v));
+    v = fmax(v, dpp_swap<0x141>(v));
+    v = fmax(v, dpp_swap<0x140>(v));
+    return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
 }
 
 // Block-wide sums of two values (or max of one), the same on every thread:
-// butterfly within each wave, then every thread adds the wave totals in wave
-// order.  The two halves of `red` alternate between calls, so one barrier per
+// the wave sums above, then every thread adds the wave totals in wave order.  The two halves of `red` alternate between calls, so one barrier per
 // reduction suffices: a buffer is rewritten only after the barrier of the
 // next reduction, which every reader of the previous contents has passed.
 template <int T>
