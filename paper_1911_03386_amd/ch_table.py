@@ -74,9 +74,12 @@ def run(L_over_pi: float, members: int = 1024, prec: int = CH_F32_BULK, t_end: f
         bs = np.array([ens.ensemble_window(20.0, t_end + 0.5 * dt, rng.integers(0, members, members))
                        for _ in range(boot)])
         se_b0, se_k = bs.std(axis=0)
-        late, _ = ens.ensemble_window(80.0, t_end + 0.5 * dt)
-        se_late = float(np.std([ens.ensemble_window(80.0, t_end + 0.5 * dt, rng.integers(0, members, members))[0]
-                                for _ in range(boot)]))
+        late, se_late = math.nan, math.nan
+        if t_end >= 80.0:
+            late, _ = ens.ensemble_window(80.0, t_end + 0.5 * dt)
+            se_late = float(np.std([ens.ensemble_window(80.0, t_end + 0.5 * dt,
+                                                        rng.integers(0, members, members))[0]
+                                    for _ in range(boot)]))
         return dict(L_over_pi=L_over_pi, n=n, members=members, steps=nsteps, wall_s=wall,
                     glups=members * n * n * nsteps / wall / 1e9, beta0=beta0, k=k, se_beta0=float(se_b0),
                     se_k=float(se_k), beta0_80_100=late, se_beta0_80_100=se_late,
