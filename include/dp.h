@@ -38,7 +38,9 @@
  * caller owns one device workspace of dp_workspace_bytes() bytes (256-byte
  * aligned) that must outlive the context; work runs on the caller's stream;
  * calls returning data to the host synchronise it; a context is not
- * re-entrant.
+ * re-entrant.  Until dp_set_radii has run, the other calls on the context
+ * (except dp_destroy and dp_last_error) return CH_ESTATE; so do calls on a
+ * destroyed or unknown context.
  */
 #ifndef DP_H_
 #define DP_H_
