@@ -111,6 +111,28 @@ def test_line_solve_dft_closed_form(orc, n, rho):
     np.testing.assert_allclose(y, ref, rtol=0, atol=1e-13 * np.abs(f).max() * max(1, rho) ** 0.5)
 
 
+@pytest.mark.parametrize("n,rho", [(512, 441.0), (512, 1764.0), (1024, 441.0), (1024, 1764.0)])
+def test_line_solve_few_ulps_and_exact_mean(orc, n, rho):
+    """Lines with a nonzero mean (0.3, as in the asymmetric ensembles) at the
+    ensembles' large rho: the solve is within a few ulps of the DFT closed
+    form, and the line mean passes through unchanged, because the periodic
+    operator fixes constants (the discrete form of the conservation of <C> in
+    Section 4).  A Woodbury solve without the mean split and the residual
+    correction misses the first bar by 7-19x and the second by 10-100x."""
+    for seed in range(3):
+        rng = np.random.default_rng(100 + seed)
+        f = 0.3 + rng.uniform(-0.05, 0.05, n)
+        theta = 2 * np.pi * np.arange(n) / n
+        sym = 1.0 + rho * (2 - 2 * np.cos(theta)) ** 2
+        ref = np.real(np.fft.ifft(np.fft.fft(f) / sym))
+        y = orc.cyclic_penta_solve(rho, f)
+        # the DFT reference itself is good to ~1e-16 |f|; conditioning grows as sqrt(rho)
+        bar = 1e-14 * np.abs(f).max() * max(1.0, (rho / 441.0) ** 0.5)
+        assert np.abs(y - ref).max() <= bar, (seed, np.abs(y - ref).max(), bar)
+        mf, my = math.fsum(f) / n, math.fsum(y) / n
+        assert abs(my - mf) <= 8 * np.spacing(mf), (seed, my - mf)
+
+
 # --------------------------------------------------------------------------
 # Whole linear step: single Fourier mode about a uniform state
 # --------------------------------------------------------------------------
@@ -195,6 +217,20 @@ def test_conservation_and_monotone_energy_c1(orc):
     F = S[:, 1]
     assert np.all(np.diff(F) <= 1e-13 * F[:-1])
     assert np.all(np.isfinite(S))
+
+
+@pytest.mark.slow
+def test_conservation_asymmetric_512_rho441(orc):
+    """<C> over 1000 steps of a 512^2 asymmetric mixture (C0 = 0.3) at
+    gamma dt / h^4 = 441, the 64 x 512^2 ensemble's setting: conserved to
+    rounding, far below steps x eps (Section 4: the periodic dynamics conserve
+    the mean; each ADI line operator fixes constants).  A line solve that
+    loses the mean at the 1e-14 level per solve drifts by about 1e-10 here."""
+    C0 = orc.init_field((512, 512), 0.3, 0.05, 77)
+    m0 = math.fsum(C0.ravel()) / C0.size
+    C = orc.step(C0, 0.01, 1e-3, 1000)
+    drift = abs(math.fsum(C.ravel()) / C.size - m0)
+    assert drift <= 1000 * np.finfo(float).eps, drift
 
 
 def test_conservation_asymmetric_3d(orc):
