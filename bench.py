@@ -8,9 +8,10 @@ second (GLUPS = sites x steps / seconds / 1e9) with the state resident in HBM,
 FP32-bulk batched ensembles against plain FP64 single grids.
 
 Prints ONE JSON line.  Default workload: the FP32-bulk batched ensemble of
-64 x 512^2 grids; the same line carries the plain FP64 single 1024^2 grid
-measured the same way ("compare"), the roofline figures of the dominant
-kernel and the oracle timed on the host cores.
+64 x 512^2 grids; the same line carries the plain FP64 single 1024^2 grid and
+the FP64 64 x 512^2 ensemble measured the same way ("compare"), the roofline
+figures of the dominant kernel and the oracle timed on the host cores.  The
+timed steps are replays of a HIP graph captured and uploaded beforehand.
 
 `--workload model1` measures the droplet-population ensembles instead (Model 1
 of the paper): the whole table of Section 3 (100 populations for each N =
@@ -50,7 +51,8 @@ def parse():
     p.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's)")
     p.add_argument("--warmup", type=int, default=100)
     p.add_argument("--workload", default="c3")
-    p.add_argument("--compare", default="c2", help="second workload reported in the same line ('' = none)")
+    p.add_argument("--compare", default="c2,c3_fp64",
+                   help="further workloads reported in the same line, comma-separated ('' = none)")
     p.add_argument("--compare-steps", type=int, default=None)
     p.add_argument("--kernel-steps", type=int, default=200,
                    help="real steps after the timed region whose kernels are timed one by one")
@@ -91,6 +93,18 @@ def measured_traffic(workload, kernel):
     return t.get("workloads", {}).get(workload, {}).get(kernel)
 
 
+def graph_len(steps, cap):
+    """Steps per captured graph: the largest g <= cap that divides the timed
+    steps (searched down to cap / 2), so that the timed region is whole graph
+    replays; cap itself if none does (the remainder then runs as direct
+    launches)."""
+    g = max(1, min(cap, steps))
+    for d in range(g, max(1, g // 2) - 1, -1):
+        if steps % d == 0:
+            return d
+    return g
+
+
 def run_gpu(wl, steps, warmup, kernel_steps, graph_steps, autotune, tune_cache):
     import torch
 
@@ -98,9 +112,12 @@ def run_gpu(wl, steps, warmup, kernel_steps, graph_steps, autotune, tune_cache):
 
     total = warmup + steps + kernel_steps + 2
     ens = Ensemble(wl.descs, prec=wl.prec, cadence=wl.cadence, max_samples=total // wl.cadence + 2)
-    ens.set_graph_steps(graph_steps)
     if autotune:
         ens.autotune(tune_cache)
+    # the graph is captured, instantiated and uploaded here, before anything
+    # is timed (tuning drops it, so this comes after the tuning)
+    gs = graph_len(steps, graph_steps)
+    ens.set_graph_steps(gs)
     ens.init_random()
     if warmup:
         ens.step(warmup)
@@ -119,7 +136,8 @@ def run_gpu(wl, steps, warmup, kernel_steps, graph_steps, autotune, tune_cache):
     plan = ens.describe()
     ens.close()
     return dict(wall=wall, gpu_ms=gpu_ms, kernel_ms=[float(x) for x in kms], plan=plan,
-                F=[float(x) for x in F[:4]])
+                F=[float(x) for x in F[:4]], graph={"steps_per_graph": gs, "replays": steps // gs,
+                                                    "direct_steps": steps % gs})
 
 
 def copy_calibration():
@@ -160,6 +178,15 @@ def cpu_baseline(wl, seconds):
         return sites * k / el / 1e9, k, el
 
     threads = oracle.num_threads()
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     v, k, el = rate(seconds)
     prev = oracle.set_num_threads(1)
     v1, k1, el1 = rate(seconds / 3)
@@ -168,6 +195,7 @@ def cpu_baseline(wl, seconds):
         "value": v,
         "unit": "GLUPS",
         "cores": threads,
+        "cpu_model": cpu_model,
         "kind": "oracle",
         "sample": f"member 0 of {wl.name} ({'x'.join(map(str, shape[::-1]))}), {k} steps, {el:.1f} s",
         "single_thread": {"value": v1, "sample": f"{k1} steps, {el1:.1f} s"},
@@ -324,34 +352,41 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": traffic,
+            "traffic_source": ("stored rocprofv3 FETCH_SIZE + WRITE_SIZE summary (profiles/traffic.json), "
+                               "taken with the current kernel sources") if traffic is not None else None,
             "alg_bytes_per_launch": alg_bytes,
             "ms_per_launch": {k: round(v, 5) for k, v in zip(kinds, kms)},
             "classes": len(r["plan"].strip().splitlines()),
             "step_frac": round(S * 4 * word * (1.5 if wl.descs[0].dim == 3 else 1.0)
                                / (r["gpu_ms"] / steps / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
         },
+        "timed_region": r["graph"],
         "plan": r["plan"].strip().splitlines(),
         "kernel_src_sha": kernel_source_sha(),
     }
-    if args.compare:
-        wc = workloads.get(args.compare)
+    compares = []
+    for cname in [c for c in args.compare.split(",") if c]:
+        wc = workloads.get(cname)
         csteps = args.compare_steps if args.compare_steps is not None else wc.steps
         rc = run_gpu(wc, csteps, args.warmup, args.kernel_steps, args.graph_steps,
                      args.autotune, args.tune_cache)
         wordc = 4 if wc.prec == CH_F32_BULK else 8
         vc = wc.sites * csteps / (rc["gpu_ms"] / 1e3) / 1e9
-        out["compare"] = {
+        compares.append({
             "workload": wc.name,
             "dtype": "f32" if wc.prec == CH_F32_BULK else "f64",
             "value": round(vc, 3),
             "unit": "GLUPS",
             "steps": csteps,
             "ms_per_step": rc["gpu_ms"] / csteps,
+            "timed_region": rc["graph"],
             "ms_per_launch": {k: round(v, 5) for k, v in zip(kinds, rc["kernel_ms"])},
             "hbm_frac_of_step": round(wc.sites * 4 * wordc * (1.5 if wc.descs[0].dim == 3 else 1.0)
                                       / (rc["gpu_ms"] / csteps / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
-            "fp32_batched_over_this": round(value / vc, 2),
-        }
+            "headline_over_this": round(value / vc, 2),
+        })
+    if compares:
+        out["compare"] = compares
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -182,7 +182,11 @@ ch_status ch_set_tiles(ch_ctx* ctx, int32_t cls, int32_t cx, int32_t rl, int32_t
                        int32_t units, int32_t cy, int32_t by, int32_t cz, int32_t bz);
 
 /* HIP graphs: with graph_steps > 0, ch_step replays a captured graph of
- * graph_steps steps (default 16); 0 launches every kernel directly.  Kernels
+ * graph_steps steps (default 16); 0 launches every kernel directly.
+ * ch_set_graph_steps captures, instantiates and uploads that graph at once
+ * (nothing runs), so the first ch_step that replays it costs no more than
+ * later ones; ch_autotune and ch_set_tiles drop it, and the next ch_step
+ * that needs it builds it again.  Kernels
  * are always launched directly on the legacy null stream (it cannot be
  * captured) and while the caller is capturing the stream itself.  A graph the
  * caller captures advances the device step counter on every replay, while the
@@ -206,7 +210,9 @@ ch_status ch_time_kernels(ch_ctx* ctx, int64_t nsteps, double* ms);
 
 /* Ensemble statistics of beta (the paper's eq. (mup) and eq. (beta0_stats),
  * and the fit of the variance growth E(dbeta^2) = k t; Sections 3.3 and 4).
- * members: nm member indices (NULL = all members); the selected members must
+ * members: nm member indices (NULL = all members; otherwise 1 <= nm <= m, the
+ * ensemble size, else CH_EINVAL before anything is enqueued; indices may
+ * repeat, e.g. a bootstrap resample); the selected members must
  * share dt, so that sample j is at t_j = jK dt for all of them.  All three
  * are computed on the device in FP64 with fixed-order sums (deterministic),
  * from the recorded F series with the same beta as ch_beta_series, and

@@ -115,7 +115,8 @@ ch_status dp_get_volumes(dp_ctx* ctx, int32_t member, double* host_dst);
 ch_status dp_series(dp_ctx* ctx, int32_t member, double* out, int64_t cap, int64_t* count);
 
 /* Ensemble statistics of beta over the listed members (members = NULL: all;
- * nm >= 1), over the samples every listed member has recorded, with the
+ * otherwise 1 <= nm <= m, the ensemble size, else CH_EINVAL before anything
+ * is enqueued; indices may repeat), over the samples every listed member has recorded, with the
  * definitions of ch.h: mu_1, central moments mu_p (eq. (mup); 1 <= pmax <= 8;
  * mu holds cap*pmax doubles, t may be NULL), the window mean beta0 of mu_1
  * and the slope k of mu_2 = k t (eq. (beta0_stats)), and the histogram of

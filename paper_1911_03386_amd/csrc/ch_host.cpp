@@ -720,9 +720,12 @@ ch_status ensure_graph(ch_ctx* ctx, int steps)
     }
     hipGraphExec_t ex = nullptr;
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    // upload it now, so that its first replay costs no more than later ones
+    if (e == hipSuccess) e = hipGraphUpload(ex, ctx->stream);
     if (e != hipSuccess) {
+        if (ex) (void)hipGraphExecDestroy(ex);
         (void)hipGraphDestroy(g);
-        return fail(ctx, CH_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+        return fail(ctx, CH_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
     }
     ctx->graph = g;
     ctx->gexec = ex;
@@ -793,7 +796,9 @@ ch_status stat_setup(ch_ctx* ctx, const int32_t* members, int32_t nm, int32_t& M
     const int m = (int)ctx->desc.size();
     std::vector<int32_t> sel;
     if (members) {
-        if (nm < 1) return fail(ctx, CH_EINVAL, "empty member selection");
+        // the device list holds m entries (indices may repeat, e.g. a
+        // bootstrap resample of the ensemble's own size)
+        if (nm < 1 || nm > m) return fail(ctx, CH_EINVAL, "member selection needs 1 <= nm <= %d, got %d", m, nm);
         sel.assign(members, members + nm);
     } else {
         sel.resize(m);
@@ -1146,6 +1151,12 @@ ch_status ch_set_graph_steps(ch_ctx* ctx, int32_t graph_steps)
     if (graph_steps < 0) return fail(ctx, CH_EINVAL, "graph_steps must be >= 0");
     ctx->graph_steps = graph_steps;
     drop_graph(ctx);
+    // capture, instantiate and upload the graph now (nothing runs), so that
+    // the first ch_step that replays it pays for none of that
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIPCHK(ctx, hipStreamIsCapturing(ctx->stream, &cap));
+    if (graph_steps > 0 && ctx->stream != nullptr && cap == hipStreamCaptureStatusNone)
+        return ensure_graph(ctx, graph_steps);
     return CH_OK;
 }
 

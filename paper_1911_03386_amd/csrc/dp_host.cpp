@@ -197,7 +197,8 @@ ch_status stat_setup(dp_ctx* ctx, const int32_t* members, int32_t nm, std::vecto
 {
     if (!ctx->started) return fail(ctx, CH_ESTATE, "radii not set");
     if (members) {
-        if (nm < 1) return fail(ctx, CH_EINVAL, "need nm >= 1");
+        // the device list holds m entries (indices may repeat)
+        if (nm < 1 || nm > ctx->m()) return fail(ctx, CH_EINVAL, "need 1 <= nm <= %d, got %d", ctx->m(), nm);
         list.assign(members, members + nm);
         for (int32_t v : list)
             if (v < 0 || v >= ctx->m()) return fail(ctx, CH_EINVAL, "member %d out of range", v);

@@ -165,4 +165,14 @@ def test_ensemble_statistics_match_oracle_definitions():
     assert abs(b0 - rb0) <= 1e-12 * abs(rb0) and abs(k - rk) <= 1e-12 * abs(rk)
     h = ens.beta_histogram(1.0, 4.0, 0.0, 1.0, 20)
     assert np.array_equal(h, S.beta_histogram(beta, t, 1.0, 4.0, 0.0, 1.0, 20))
+    # selections longer than the ensemble are refused; repeats up to its size are fine
+    from paper_1911_03386_amd.dp import DpError
+
+    with pytest.raises(DpError):
+        ens.ensemble_moments(members=[0] * 13, pmax=2)
+    with pytest.raises(DpError):
+        ens.ensemble_window(1.0, 4.0, members=list(range(12)) + [5])
+    _, mub = ens.ensemble_moments(members=[4] * 12, pmax=2)
+    _, mu4 = ens.ensemble_moments(members=[4], pmax=2)
+    np.testing.assert_allclose(mub[:, 0], mu4[:, 0], rtol=1e-14, atol=1e-16)
     ens.close()

@@ -101,6 +101,19 @@ def test_statistics_errors(runs):
         ens.beta_histogram(0.0, 1.0, 1.0, 0.0, 4)
     with pytest.raises(ChError):
         ens.ensemble_window(2.0, 1.0)
+    # a selection longer than the ensemble is refused before anything runs;
+    # one of the ensemble's own size may repeat members (a bootstrap resample)
+    with pytest.raises(ChError) as e:
+        ens.ensemble_moments(members=[0] * (M + 1), pmax=2)
+    assert "nm" in str(e.value)
+    for call in (lambda: ens.ensemble_window(0.0, 2.0, members=list(range(M)) + [0]),
+                 lambda: ens.beta_histogram(0.0, 2.0, 0.0, 1.0, 4, members=[1] * (M + 1))):
+        with pytest.raises(ChError):
+            call()
+    boot = [3] * M
+    _, mub = ens.ensemble_moments(members=boot, pmax=2)
+    _, mu3 = ens.ensemble_moments(members=[3], pmax=2)
+    np.testing.assert_allclose(mub[:, 0], mu3[:, 0], rtol=1e-14, atol=1e-16)
     mixed = Ensemble([make_desc(SHAPE, 0.01, 1e-3, seed=1), make_desc(SHAPE, 0.01, 5e-4, seed=2)],
                      prec=CH_F64, cadence=K, max_samples=3)
     mixed.init_random()
