@@ -253,6 +253,45 @@ ch_status ch_destroy(ch_ctx* ctx);
  * (and ikappa, A^chunk, W derived from them). */
 ch_status ch_solver_coefficients(double rho, int32_t n, int32_t chunk, int32_t prec, double* out);
 
+/* ---- Allocation-free stepping ----------------------------------------------
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): no context and no workspace.  Advances
+ * fields the caller owns by nsteps steps of the scheme above (the same kernels
+ * as ch_step, with the default tile shapes).  The scratch these kernels need
+ * (the x-solve output field, the coefficient table, the diagnostic partials,
+ * the step counter) lives in one static device array of
+ * CH_STATIC_SCRATCH_BYTES bytes per GPU, which each GPU the library runs on
+ * holds from the library's first use there until the process ends.  The call
+ * performs no hipMalloc, hipFree or other allocation.
+ *
+ *  members   m host descriptors, 1 <= m <= CH_STATIC_MAX_MEMBERS, as for
+ *            ch_create, all with the dimension and grid (n[]) of member 0;
+ *            seed, c0 and noise are not used.
+ *  d_field   device array, 16-byte aligned: member i's field starts at element
+ *            i * S, S = n[0] n[1] n[2], x-fastest; double (CH_F64) or float
+ *            (CH_F32_BULK).  Advanced in place.
+ *  d_energy  device array of 4 m doubles, or NULL.  After the last step:
+ *            [4i] = F (quarter prefactor), [4i+1] = <C>, [4i+2] = G_id,
+ *            [4i+3] = nsteps; a non-finite state gives a non-finite F.
+ *  hip_stream  everything is enqueued on it, asynchronously (NULL = null stream).
+ *
+ * CH_EINVAL / CH_EUNSUPPORTED for bad descriptors, differing grids, m out of
+ * range, a NULL or misaligned d_field, or nsteps < 0; CH_ENOMEM when the
+ * scratch of this ensemble (about S m bytes per byte of element, plus tables)
+ * exceeds CH_STATIC_SCRATCH_BYTES.  Nothing is enqueued on an error; the
+ * message is in ch_last_error(NULL).
+ *
+ * Every call on a GPU shares that GPU's scratch array, and the array keeps the
+ * last call's contents (each call resets the counter, flags and series it
+ * uses).  Calls that overlap on one GPU (other streams, or other host threads
+ * without ordering between them) race on the array and give wrong results:
+ * serialise them.  The coefficient table goes up with a host-to-device copy
+ * from library memory, so the call cannot be captured into a graph. */
+#define CH_STATIC_SCRATCH_BYTES ((size_t)80 << 20)
+#define CH_STATIC_MAX_MEMBERS 64
+ch_status ch_step_static(const ch_member_desc* members, int32_t m, ch_precision prec, void* d_field,
+                         int64_t nsteps, double* d_energy, void* hip_stream);
+
 /* Last error message of ctx, or of the calling thread when ctx == NULL. */
 const char* ch_last_error(const ch_ctx* ctx);
 

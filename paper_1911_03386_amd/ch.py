@@ -32,7 +32,12 @@ EXPORTED = (
     "ch_set_graph_steps", "ch_describe", "ch_time_kernels", "ch_destroy", "ch_last_error",
     "ch_version", "ch_solver_coefficients", "ch_num_classes", "ch_set_tiles",
     "ch_ensemble_moments", "ch_ensemble_window", "ch_beta_histogram", "ch_sync_step",
+    "ch_step_static",
 )
+
+# Allocation-free stepping (ch_step_static): limits of its static device scratch
+CH_STATIC_SCRATCH_BYTES = 80 << 20
+CH_STATIC_MAX_MEMBERS = 64
 
 
 class ChError(RuntimeError):
@@ -96,6 +101,8 @@ def load() -> ctypes.CDLL:
         "ch_num_classes": (ctypes.c_int, [vp, P(ctypes.c_int32)]),
         "ch_set_tiles": (ctypes.c_int, [vp] + [ctypes.c_int32] * 9),
         "ch_sync_step": (ctypes.c_int, [vp, i64p]),
+        "ch_step_static": (ctypes.c_int, [P(ch_member_desc), ctypes.c_int32, ctypes.c_int, vp,
+                                          ctypes.c_int64, vp, vp]),
         "ch_ensemble_moments": (ctypes.c_int, [vp, P(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32, dp,
                                                dp, ctypes.c_int64, i64p]),
         "ch_ensemble_window": (ctypes.c_int, [vp, P(ctypes.c_int32), ctypes.c_int32, ctypes.c_double,
@@ -164,6 +171,23 @@ def ch_solver_coefficients(rho: float, n: int, chunk: int, prec: int = CH_F64) -
     out = np.zeros(11, dtype=np.float64)
     _check(load().ch_solver_coefficients(rho, n, chunk, prec, _dp(out)))
     return out
+
+
+def ch_step_static(descs, prec, field, nsteps: int, energy=None, stream=None):
+    """Advance the device tensor `field` (members back to back, each x-fastest,
+    float64 for CH_F64 or float32 for CH_F32_BULK) in place by nsteps steps
+    without any device allocation; `energy` (optional float64 device tensor of
+    4 * len(descs) values) receives F, <C>, G_id and nsteps per member.
+    Enqueued on `stream` (a torch stream; None = torch's current stream)."""
+    import torch
+
+    arr = desc_array(descs)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    st = load().ch_step_static(arr, len(descs), prec, ctypes.c_void_p(field.data_ptr()), nsteps,
+                               ctypes.c_void_p(energy.data_ptr()) if energy is not None else None,
+                               ctypes.c_void_p(stream.cuda_stream))
+    _check(st)
 
 
 @dataclass

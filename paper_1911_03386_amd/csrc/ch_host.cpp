@@ -51,6 +51,7 @@ struct ColPlan {
 struct ClassPlan {
     int dim = 2, nx = 0, ny = 0, nz = 1;
     std::vector<int> members;
+    int nfixed = 0;  // member count of a plan built without a member list (ch_step_static)
     // pass A
     int cx = 0, rl = 1, waves = 4, units = 1, P = 0, rpw = 0, R = 0, bands = 0, pitch = 0;
     int64_t bpmA = 0;  // pass-A blocks per member
@@ -71,6 +72,8 @@ struct Layout {
 };
 
 int elem_size(int prec) { return prec == 0 ? 8 : 4; }
+
+int64_t class_size(const ClassPlan& c) { return c.nfixed > 0 ? c.nfixed : (int64_t)c.members.size(); }
 
 int lds_pos(int xx, int cx, int pad) { return xx + (xx / cx) * pad; }
 
@@ -111,7 +114,7 @@ bool planA(ClassPlan& c, int prec, int cx, int rl, int waves, int units)
         c.bpmA = (c.bands + units - 1) / units;
     else
         c.bpmA = (int64_t)c.bands * ((c.nz + units - 1) / units);
-    c.nblocksA = (int64_t)c.members.size() * c.bpmA;
+    c.nblocksA = class_size(c) * c.bpmA;
     return true;
 }
 
@@ -137,7 +140,7 @@ bool planCol(ClassPlan& c, int prec, int axis, int cy, int b)
         p.cols = (int64_t)c.nx * c.ny;
         p.outer = c.nx;
     }
-    p.nblocks = (int64_t)c.members.size() * (p.cols / b);
+    p.nblocks = class_size(c) * (p.cols / b);
     return true;
 }
 
@@ -470,33 +473,36 @@ ch_status fail(ch_ctx* ctx, ch_status st, const char* fmt, ...)
             return fail(ctx, CH_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
     } while (0)
 
+// Device-table entry of one member: spacings, parameters and the line-solve
+// coefficients of every used axis for the chunk lengths of its class plan.
+void fill_member(const ch_member_desc& d, int64_t off, const ClassPlan& c, int prec, MemberDev& md)
+{
+    md = MemberDev{};
+    md.off = off;
+    md.sites = (int64_t)d.n[0] * d.n[1] * (d.dim == 3 ? d.n[2] : 1);
+    md.vol = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        const bool used = a < d.dim;
+        md.h[a] = used ? d.L[a] / d.n[a] : 1.0;
+        md.ih2[a] = used ? 1.0 / (md.h[a] * md.h[a]) : 0.0;
+        if (used) md.vol *= md.h[a];
+    }
+    md.gamma = d.gamma;
+    md.dt = d.dt;
+    for (int a = 0; a < d.dim; ++a) {
+        const double h2 = md.h[a] * md.h[a];
+        const double rho = d.gamma * d.dt / (h2 * h2);
+        const int chunk = a == 0 ? c.cx : c.col[a].cy;
+        axis_coef(rho, d.n[a], chunk, prec, md.ax[a]);
+    }
+}
+
 void fill_member_table(ch_ctx* ctx)
 {
     const int m = (int)ctx->desc.size();
     ctx->mem.assign(m, MemberDev{});
-    for (auto& c : ctx->classes) {
-        for (int gi : c.members) {
-            const ch_member_desc& d = ctx->desc[gi];
-            MemberDev& md = ctx->mem[gi];
-            md.off = ctx->L.moff[gi];
-            md.sites = (int64_t)d.n[0] * d.n[1] * (d.dim == 3 ? d.n[2] : 1);
-            md.vol = 1.0;
-            for (int a = 0; a < 3; ++a) {
-                const bool used = a < d.dim;
-                md.h[a] = used ? d.L[a] / d.n[a] : 1.0;
-                md.ih2[a] = used ? 1.0 / (md.h[a] * md.h[a]) : 0.0;
-                if (used) md.vol *= md.h[a];
-            }
-            md.gamma = d.gamma;
-            md.dt = d.dt;
-            for (int a = 0; a < d.dim; ++a) {
-                const double h2 = md.h[a] * md.h[a];
-                const double rho = d.gamma * d.dt / (h2 * h2);
-                const int chunk = a == 0 ? c.cx : c.col[a].cy;
-                axis_coef(rho, d.n[a], chunk, ctx->prec, md.ax[a]);
-            }
-        }
-    }
+    for (auto& c : ctx->classes)
+        for (int gi : c.members) fill_member(ctx->desc[gi], ctx->L.moff[gi], c, ctx->prec, ctx->mem[gi]);
 }
 
 ch_status upload_tables(ch_ctx* ctx)
@@ -836,6 +842,58 @@ bool window_range(const ch_ctx* ctx, double dt, int64_t J, double t1, double t2,
         }
     }
     return j0 >= 0;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Allocation-free stepping (ch_step_static): its scratch is one static device
+// array per GPU.  Host code never passes `scratch` itself to a kernel (in host
+// code the name is only a stand-in for the device symbol): the device address
+// is taken once per device with hipGetSymbolAddress and kept in
+// g_static_ptr, and only that address is used.
+// ===========================================================================
+static __device__ __align__(256) unsigned char scratch[CH_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kStaticMaxDevices = 64;
+std::mutex g_static_mu;  // guards the per-device addresses and the host staging tables
+void* g_static_ptr[kStaticMaxDevices] = {};
+// host staging of the member table and class member list (no heap use per call)
+MemberDev g_static_mem[CH_STATIC_MAX_MEMBERS];
+int32_t g_static_mids[CH_STATIC_MAX_MEMBERS];
+
+// Offsets (bytes) of the parts of the static scratch for one call.
+struct StaticLayout {
+    size_t mem = 0, mids = 0, W = 0, partials = 0, steps = 0, nstamp = 0, flags = 0, series = 0,
+           energy = 0, total = 0;
+};
+
+StaticLayout static_layout(const ClassPlan& c, int prec, int32_t m, int64_t sites)
+{
+    StaticLayout S;
+    size_t o = 0;
+    S.mem = o;
+    o = align_up(o + sizeof(MemberDev) * m);
+    S.mids = o;
+    o = align_up(o + sizeof(int32_t) * m);
+    S.W = o;
+    o = align_up(o + (size_t)elem_size(prec) * (size_t)sites * m);
+    S.partials = o;
+    o = align_up(o + sizeof(double) * 3 * (size_t)c.nblocksA);
+    S.steps = o;
+    o = align_up(o + sizeof(int64_t));
+    S.nstamp = o;
+    o = align_up(o + sizeof(int64_t));
+    S.flags = o;
+    o = align_up(o + sizeof(int32_t) * m);
+    S.series = o;
+    o = align_up(o + sizeof(double) * kSeriesSlots * m);  // one sample per member
+    S.energy = o;
+    o = align_up(o + sizeof(double) * 4 * m);
+    S.total = o;
+    return S;
 }
 
 }  // namespace
@@ -1574,6 +1632,162 @@ ch_status ch_solver_coefficients(double rho, int32_t n, int32_t chunk, int32_t p
     out[2] = c.ikappa;
     for (int i = 0; i < 4; ++i) out[3 + i] = c.M[i];
     for (int i = 0; i < 4; ++i) out[7 + i] = c.W[i];
+    return CH_OK;
+}
+
+ch_status ch_step_static(const ch_member_desc* members, int32_t m, ch_precision prec, void* d_field,
+                         int64_t nsteps, double* d_energy, void* hip_stream)
+{
+    // Diagnostics cadence of the step kernels: only step 0 is a sample step
+    // (its partials are reduced into the one-sample series in scratch); the
+    // energies of the final state come from a diagnostics pass at the end.
+    constexpr int32_t kNoCadence = 1 << 30;
+    std::string err;
+    if (m < 1 || m > CH_STATIC_MAX_MEMBERS)
+        return fail(nullptr, CH_EINVAL, "m = %d outside 1..%d", m, CH_STATIC_MAX_MEMBERS);
+    ch_status st = validate(members, m, prec, kNoCadence, 1, err);
+    if (st != CH_OK) return fail(nullptr, st, "%s", err.c_str());
+    for (int i = 1; i < m; ++i)
+        if (members[i].dim != members[0].dim || members[i].n[0] != members[0].n[0] ||
+            members[i].n[1] != members[0].n[1] || members[i].n[2] != members[0].n[2])
+            return fail(nullptr, CH_EINVAL, "member %d: every member needs the grid of member 0", i);
+    if (!d_field) return fail(nullptr, CH_EINVAL, "d_field is NULL");
+    if (reinterpret_cast<uintptr_t>(d_field) % 16)
+        return fail(nullptr, CH_EINVAL, "d_field must be 16-byte aligned");
+    if (reinterpret_cast<uintptr_t>(d_energy) % 8) return fail(nullptr, CH_EINVAL, "d_energy must be 8-byte aligned");
+    if (nsteps < 0) return fail(nullptr, CH_EINVAL, "nsteps must be >= 0");
+
+    const ch_member_desc& d0 = members[0];
+    ClassPlan c;
+    c.dim = d0.dim;
+    c.nx = d0.n[0];
+    c.ny = d0.n[1];
+    c.nz = d0.dim == 3 ? d0.n[2] : 1;
+    c.nfixed = m;
+    if (!default_A(c, prec) || !default_col(c, prec, 1) || (c.dim == 3 && !default_col(c, prec, 2)))
+        return fail(nullptr, CH_EUNSUPPORTED, "no tile shape fits this grid in LDS");
+    const int64_t sites = (int64_t)c.nx * c.ny * c.nz;
+    const StaticLayout S = static_layout(c, prec, m, sites);
+    if (S.total > CH_STATIC_SCRATCH_BYTES)
+        return fail(nullptr, CH_ENOMEM,
+                    "%d members of %lld sites need %zu bytes of static scratch; the maximum is %zu "
+                    "(use ch_create with a workspace instead)",
+                    m, (long long)sites, S.total, (size_t)CH_STATIC_SCRATCH_BYTES);
+
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, CH_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kStaticMaxDevices) return fail(nullptr, CH_EDEVICE, "device %d not supported", dev);
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        // first call on this device (it is current): the device address of its
+        // copy of the static array
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(nullptr, CH_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_static_ptr[dev] = p;
+    }
+    char* base = static_cast<char*>(g_static_ptr[dev]);
+    for (int i = 0; i < m; ++i) {
+        fill_member(members[i], (int64_t)i * sites, c, prec, g_static_mem[i]);
+        g_static_mids[i] = i;
+    }
+    // pageable host-to-device copies: the staging tables are read before the
+    // calls return, so the next call may refill them
+    if ((e = hipMemcpyAsync(base + S.mem, g_static_mem, sizeof(MemberDev) * m, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(base + S.mids, g_static_mids, sizeof(int32_t) * m, hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+        return fail(nullptr, CH_EDEVICE, "table upload: %s", hipGetErrorString(e));
+
+    int64_t* steps = reinterpret_cast<int64_t*>(base + S.steps);
+    int64_t* nstamp = reinterpret_cast<int64_t*>(base + S.nstamp);
+    int32_t* flags = reinterpret_cast<int32_t*>(base + S.flags);
+    double* series = reinterpret_cast<double*>(base + S.series);
+    // the scratch keeps the previous call's contents: counter, flags and series start afresh
+    if ((e = launch_reset(steps, 1, 0, flags, m, series, (int64_t)kSeriesSlots * m, s)) != hipSuccess)
+        return fail(nullptr, CH_EDEVICE, "reset: %s", hipGetErrorString(e));
+
+    PassAArgs a{};
+    a.C = d_field;
+    a.W = base + S.W;
+    a.mem = reinterpret_cast<const MemberDev*>(base + S.mem);
+    a.mids = reinterpret_cast<const int32_t*>(base + S.mids);
+    a.nmem = m;
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.nz = c.nz;
+    a.P = c.P;
+    a.rows_per_wave = c.rpw;
+    a.waves = c.waves;
+    a.R = c.R;
+    a.bands_y = c.bands;
+    a.units = c.units;
+    a.blocks_per_member = c.bpmA;
+    a.nblocks = c.nblocksA;
+    a.pitch = c.pitch;
+    a.conv = CH_ENERGY_QUARTER;
+    a.K = kNoCadence;
+    a.step = steps;
+    a.partials = reinterpret_cast<double*>(base + S.partials);
+    a.nstamp = nstamp;
+
+    FinArgs f{};
+    f.enabled = 1;
+    f.mem = a.mem;
+    f.mids = a.mids;
+    f.nmem = m;
+    f.K = kNoCadence;
+    f.blocks_per_member = c.bpmA;
+    f.partials = a.partials;
+    f.nstamp = nstamp;
+    f.max_samples = 1;
+    f.step = steps;
+    f.series = series;
+    f.energy_now = d_energy ? d_energy : reinterpret_cast<double*>(base + S.energy);
+    f.flags = flags;
+
+    auto col = [&](int axis, const void* src, void* dst, bool last) {
+        const ColPlan& p = c.col[axis];
+        ColArgs ca{};
+        ca.src = src;
+        ca.dst = dst;
+        ca.mem = a.mem;
+        ca.mids = a.mids;
+        ca.axis = axis;
+        ca.n = axis == 1 ? c.ny : c.nz;
+        ca.stride = p.stride;
+        ca.nx = c.nx;
+        ca.outer = p.outer;
+        ca.cols = p.cols;
+        ca.b = p.b;
+        ca.P = p.P;
+        ca.nblocks = p.nblocks;
+        if (last) {
+            ca.fin = f;
+            ca.fin.mode = MODE_STEP;
+            ca.fin.G = (int32_t)std::min<int64_t>(std::min<int64_t>(m, 1024), p.nblocks);
+        }
+        return launch_col(prec, p.cy, ca, s);
+    };
+    for (int64_t i = 0; i < nsteps; ++i) {
+        a.mode = MODE_STEP;
+        if ((e = launch_passA(prec, c.dim, c.cx, c.rl, c.units, a, c.ldsA, s)) != hipSuccess) break;
+        if ((e = col(1, a.W, c.dim == 2 ? d_field : a.W, c.dim == 2)) != hipSuccess) break;
+        if (c.dim == 3 && (e = col(2, a.W, d_field, true)) != hipSuccess) break;
+    }
+    if (e == hipSuccess && d_energy) {
+        // F, <C> and G_id of the final state, and the step count
+        a.mode = MODE_DIAG;
+        f.mode = MODE_DIAG;
+        f.G = (int32_t)std::min<int32_t>(m, 1024);
+        e = launch_passA(prec, c.dim, c.cx, c.rl, c.units, a, c.ldsA, s);
+        if (e == hipSuccess) e = launch_fin(f, s);
+    }
+    if (e != hipSuccess) return fail(nullptr, CH_EDEVICE, "launch: %s", hipGetErrorString(e));
     return CH_OK;
 }
 

@@ -249,3 +249,34 @@ def test_droplet_create_rejects_bad_workspace_before_any_device_call():
     bogus = ctypes.c_void_p(0x1000)
     assert L.dp_advance(bogus, 1) == dp.CH_ESTATE
     assert L.dp_destroy(None) == dp.CH_EINVAL
+
+
+class _FakeTensor:
+    """Stands in for a device tensor: only its address is passed, and every
+    case below is refused before the library touches the device."""
+
+    def __init__(self, ptr):
+        self._ptr = ptr
+
+    def data_ptr(self):
+        return self._ptr
+
+
+class _FakeStream:
+    cuda_stream = 0
+
+
+@pytest.mark.parametrize("descs,ptr,nsteps,status,frag", [
+    ([], 256, 1, ch.CH_EINVAL, "outside"),
+    ([_desc()] * 65, 256, 1, ch.CH_EINVAL, "outside"),
+    ([_desc(), _desc(n=(64, 32))], 256, 1, ch.CH_EINVAL, "grid of member 0"),
+    ([_desc()], 0, 1, ch.CH_EINVAL, "NULL"),
+    ([_desc()], 8, 1, ch.CH_EINVAL, "aligned"),
+    ([_desc()], 256, -1, ch.CH_EINVAL, "nsteps"),
+    ([_desc(n=(7, 64))], 256, 1, ch.CH_EUNSUPPORTED, "unsupported"),
+    ([_desc(n=(1024, 1024))] * 32, 256, 1, ch.CH_ENOMEM, "static scratch"),
+])
+def test_step_static_validation(descs, ptr, nsteps, status, frag):
+    with pytest.raises(ch.ChError) as e:
+        ch.ch_step_static(descs, ch.CH_F32_BULK, _FakeTensor(ptr), nsteps, stream=_FakeStream())
+    assert e.value.status == status and frag in str(e.value), str(e.value)
