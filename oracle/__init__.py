@@ -70,6 +70,9 @@ def lib():
         L.orc_step.restype = ctypes.c_int
         L.orc_step.argtypes = [ctypes.c_int, ip, dp, ctypes.c_double, ctypes.c_double, dp,
                                ctypes.c_int64]
+        L.orc_step_theta.restype = ctypes.c_int
+        L.orc_step_theta.argtypes = [ctypes.c_int, ip, dp, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, dp, ctypes.c_int64]
         L.orc_energy.restype = ctypes.c_double
         L.orc_energy.argtypes = [ctypes.c_int, ip, dp, ctypes.c_double, ctypes.c_int, dp]
         L.orc_mean.restype = ctypes.c_double
@@ -80,6 +83,10 @@ def lib():
         L.orc_run_series.argtypes = [ctypes.c_int, ip, dp, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int, ctypes.c_int32, ctypes.c_int64, dp, dp,
                                      ctypes.c_int64]
+        L.orc_run_series_theta.restype = ctypes.c_int64
+        L.orc_run_series_theta.argtypes = [ctypes.c_int, ip, dp, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int, ctypes.c_int32, ctypes.c_int64,
+                                           dp, dp, ctypes.c_int64]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
         L.orc_set_num_threads.restype = ctypes.c_int
@@ -167,11 +174,13 @@ def rhs(C: np.ndarray, gamma: float, dt: float, L=2 * np.pi) -> np.ndarray:
     return out
 
 
-def step(C: np.ndarray, gamma: float, dt: float, nsteps: int = 1, L=2 * np.pi) -> np.ndarray:
-    """Return C advanced by nsteps ADI steps (input left untouched)."""
+def step(C: np.ndarray, gamma: float, dt: float, nsteps: int = 1, L=2 * np.pi,
+         theta: float = 1.0) -> np.ndarray:
+    """Return C advanced by nsteps ADI steps (input left untouched); theta = 1
+    is the implicit ADI scheme, theta = 1/2 its Crank-Nicolson variant."""
     C = np.array(C, dtype=np.float64, order="C", copy=True)
     dim, n = _dims(C.shape)
-    rc = lib().orc_step(dim, _ip(n), _dp(_lengths(dim, L)), gamma, dt, _dp(C), nsteps)
+    rc = lib().orc_step_theta(dim, _ip(n), _dp(_lengths(dim, L)), gamma, dt, theta, _dp(C), nsteps)
     if rc != 0:
         raise RuntimeError(f"orc_step failed ({rc})")
     return C
@@ -199,14 +208,14 @@ SERIES_COLUMNS = ("t", "F", "dFdt", "dFdt_identity", "beta", "meanC")
 
 
 def run_series(C: np.ndarray, gamma: float, dt: float, nsteps: int, K: int = 10,
-               L=2 * np.pi, conv: int = ENERGY_QUARTER):
+               L=2 * np.pi, conv: int = ENERGY_QUARTER, theta: float = 1.0):
     """Run nsteps from C; return (final C, samples[J, 6]) with SERIES_COLUMNS."""
     C = np.array(C, dtype=np.float64, order="C", copy=True)
     dim, n = _dims(C.shape)
     J = nsteps // K + 1
     out = np.full((J, 6), np.nan, dtype=np.float64)
-    got = lib().orc_run_series(dim, _ip(n), _dp(_lengths(dim, L)), gamma, dt, conv, K,
-                               nsteps, _dp(C), _dp(out), J)
+    got = lib().orc_run_series_theta(dim, _ip(n), _dp(_lengths(dim, L)), gamma, dt, theta, conv, K,
+                                     nsteps, _dp(C), _dp(out), J)
     if got != J:
         raise RuntimeError(f"orc_run_series failed ({got})")
     return C, out

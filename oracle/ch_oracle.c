@@ -21,6 +21,15 @@
  *   C^n+1 = w^D
  *
  * with D_d f = (f_{+1} - 2 f + f_{-1}) / h_d^2 (periodic), lap_h = sum_d D_d.
+ * This is theta = 1 of the theta-weighted ADI family
+ *
+ *   prod_d (I + theta gamma dt D_d^2) C^{n+1}
+ *       = prod_d (I - (1-theta) gamma dt D_d^2) C^n + RHS - C^n,
+ *
+ * whose theta = 1/2 member is the Crank-Nicolson ADI variant: second order in
+ * dt where only the pure fourth derivatives act (Appendix A: the scheme for
+ * hyper-diffusion alone is second order), first order once the explicit
+ * nonlinear and mixed terms enter (orc_step_theta).
  *
  * Diagnostics (eq. (dFdt_ch), eq. (betadef)):
  *   F      = prod(h) sum_sites [ e(C) + gamma/2 sum_d ((C_{+d}-C)/h_d)^2 ]
@@ -85,7 +94,8 @@ void orc_init_field(int dim, const int32_t *n, double c0, double noise, uint64_t
 
 /* ------------------------------------------------------------------ */
 /* Exactly rounded summation: Shewchuk (1997) non-overlapping partials,  */
-/* with the round-half-even fix-up used by correctly rounded fsum.       */
+/* with the round-half-even fix-up of the final partials that CPython's  */
+/* math.fsum applies (R. Hettinger's msum recipe built on Shewchuk).     */
 /* ------------------------------------------------------------------ */
 typedef struct {
     double p[160];
@@ -442,11 +452,11 @@ int orc_cyclic_penta_solve(int64_t n, double rho, const double *f, double *y)
     return 0;
 }
 
-/* solve (I + gamma dt D_d^2) on every d-line of u, in place */
-static int sweep(const grid *g, int d, double gamma, double dt, double *u)
+/* solve (I + theta gamma dt D_d^2) on every d-line of u, in place */
+static int sweep(const grid *g, int d, double gamma, double dt, double theta, double *u)
 {
     double h2 = g->h[d] * g->h[d];
-    double rho = gamma * dt / (h2 * h2);
+    double rho = theta * gamma * dt / (h2 * h2);
     penta q;
     if (penta_setup(&q, g->n[d], rho) != 0) {
         penta_free(&q);
@@ -473,6 +483,22 @@ static int sweep(const grid *g, int d, double gamma, double dt, double *u)
     return 0;
 }
 
+/* u <- (I - c gamma dt D_d^2) u along axis d (explicit half of the
+   Crank-Nicolson factor), D_d^2 = [1, -4, 6, -4, 1] / h^4 */
+static void apply_explicit(const grid *g, int d, double c, double gamma, double dt, double *u)
+{
+    double h2 = g->h[d] * g->h[d];
+    double r = c * gamma * dt / (h2 * h2);
+    double *v = (double *)malloc(sizeof(double) * g->S);
+    memcpy(v, u, sizeof(double) * g->S);
+    for (int64_t s = 0; s < g->S; s++) {
+        double d4 = v[nb(g, s, d, -2)] - 4.0 * v[nb(g, s, d, -1)] + 6.0 * v[s] - 4.0 * v[nb(g, s, d, 1)] +
+                    v[nb(g, s, d, 2)];
+        u[s] = v[s] - r * d4;
+    }
+    free(v);
+}
+
 /* ------------------------------------------------------------------ */
 /* One member's state and the time step                                 */
 /* ------------------------------------------------------------------ */
@@ -494,25 +520,49 @@ void orc_rhs(int dim, const int32_t *n, const double *L, double gamma, double dt
     free(X);
 }
 
-/* advance C by nsteps steps of the ADI scheme; returns 0 on success */
-int orc_step(int dim, const int32_t *n, const double *L, double gamma, double dt, double *C,
-             int64_t nsteps)
+/* advance C by nsteps steps of the theta-weighted ADI scheme
+ *   prod_d (I + theta gamma dt D_d^2) C^{n+1}
+ *       = prod_d (I - (1-theta) gamma dt D_d^2) C^n + dt lap_h(C^3 - C) - 2 gamma dt sum_{d<e} D_d D_e C^n
+ * theta = 1: the implicit (backward Euler) ADI step; theta = 1/2: the
+ * Crank-Nicolson ADI step.  Returns 0 on success. */
+int orc_step_theta(int dim, const int32_t *n, const double *L, double gamma, double dt, double theta,
+                   double *C, int64_t nsteps)
 {
     grid g;
     grid_make(&g, dim, n, L);
     double *w = (double *)malloc(sizeof(double) * g.S);
-    if (!w) return -1;
+    double *e = (double *)malloc(sizeof(double) * g.S);
+    if (!w || !e) {
+        free(w);
+        free(e);
+        return -1;
+    }
     for (int64_t k = 0; k < nsteps; k++) {
-        orc_rhs(dim, n, L, gamma, dt, C, w);
+        orc_rhs(dim, n, L, gamma, dt, C, w); /* C + explicit terms */
+        if (theta != 1.0) {
+            /* replace the leading C by prod_d (I - (1-theta) gamma dt D_d^2) C */
+            memcpy(e, C, sizeof(double) * g.S);
+            for (int d = 0; d < dim; d++) apply_explicit(&g, d, 1.0 - theta, gamma, dt, e);
+            for (int64_t s = 0; s < g.S; s++) w[s] = e[s] + (w[s] - C[s]);
+        }
         for (int d = 0; d < dim; d++)
-            if (sweep(&g, d, gamma, dt, w) != 0) {
+            if (sweep(&g, d, gamma, dt, theta, w) != 0) {
                 free(w);
+                free(e);
                 return -2;
             }
         memcpy(C, w, sizeof(double) * g.S);
     }
     free(w);
+    free(e);
     return 0;
+}
+
+/* advance C by nsteps steps of the implicit ADI scheme (theta = 1) */
+int orc_step(int dim, const int32_t *n, const double *L, double gamma, double dt, double *C,
+             int64_t nsteps)
+{
+    return orc_step_theta(dim, n, L, gamma, dt, 1.0, C, nsteps);
 }
 
 /* ------------------------------------------------------------------ */
@@ -580,9 +630,9 @@ double orc_dFdt_identity(int dim, const int32_t *n, const double *L, double gamm
 /* C is advanced in place.  Returns the number of samples written, or    */
 /* a negative value on error.                                           */
 /* ------------------------------------------------------------------ */
-int64_t orc_run_series(int dim, const int32_t *n, const double *L, double gamma, double dt,
-                       int conv, int32_t K, int64_t nsteps, double *C, double *out,
-                       int64_t cap)
+int64_t orc_run_series_theta(int dim, const int32_t *n, const double *L, double gamma, double dt,
+                             double theta, int conv, int32_t K, int64_t nsteps, double *C, double *out,
+                             int64_t cap)
 {
     if (K < 1 || nsteps < 0) return -1;
     int64_t J = nsteps / K + 1;
@@ -609,7 +659,7 @@ int64_t orc_run_series(int dim, const int32_t *n, const double *L, double gamma,
             if (k >= 1 && (k - 1) % K == 0) Fp[(k - 1) / K] = F;
             if ((k + 1) % K == 0 && (k + 1) / K < J) Fm[(k + 1) / K] = F;
         }
-        if (k < nsteps && orc_step(dim, n, L, gamma, dt, C, 1) != 0) {
+        if (k < nsteps && orc_step_theta(dim, n, L, gamma, dt, theta, C, 1) != 0) {
             free(Fm);
             free(F0);
             free(Fp);
@@ -635,6 +685,13 @@ int64_t orc_run_series(int dim, const int32_t *n, const double *L, double gamma,
     free(F0);
     free(Fp);
     return J;
+}
+
+int64_t orc_run_series(int dim, const int32_t *n, const double *L, double gamma, double dt,
+                       int conv, int32_t K, int64_t nsteps, double *C, double *out,
+                       int64_t cap)
+{
+    return orc_run_series_theta(dim, n, L, gamma, dt, 1.0, conv, K, nsteps, C, out, cap);
 }
 
 int orc_num_threads(void)

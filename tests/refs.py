@@ -66,14 +66,18 @@ def semi_discrete_flow(C0: np.ndarray, gamma: float, T: float, dt: float, L=2 * 
     return np.real(ifftn(v))
 
 
-def amplification(k, n, L, gamma, dt, c0):
-    """Closed-form growth factor of the linearised ADI step for the single
-    Fourier mode cos(k.x) about the uniform state c0 (2D or 3D)."""
+def amplification(k, n, L, gamma, dt, c0, theta=1.0):
+    """Closed-form growth factor of the linearised theta-weighted ADI step
+    (theta = 1: implicit, 1/2: Crank-Nicolson) for the single Fourier mode
+    cos(k.x) about the uniform state c0 (2D or 3D)."""
     lam = [(4.0 * n[d] ** 2 / L**2) * np.sin(np.pi * k[d] / n[d]) ** 2 for d in range(len(k))]
-    num = 1.0 - dt * sum(lam) * (3 * c0**2 - 1)
+    num = 1.0
+    for d in range(len(k)):
+        num *= 1.0 - (1.0 - theta) * gamma * dt * lam[d] ** 2
+    num -= dt * sum(lam) * (3 * c0**2 - 1)
     cross = sum(lam[d] * lam[e] for d in range(len(k)) for e in range(d + 1, len(k)))
     num -= 2 * gamma * dt * cross
     den = 1.0
     for d in range(len(k)):
-        den *= 1.0 + gamma * dt * lam[d] ** 2
+        den *= 1.0 + theta * gamma * dt * lam[d] ** 2
     return num / den
