@@ -154,6 +154,23 @@ ch_status ch_beta_series(ch_ctx* ctx, int32_t member, double* t, double* F, doub
                          double* dFdt_identity, double* beta, double* meanC, int64_t cap,
                          int64_t* count);
 
+/* Time scheme.  theta = 1 (default): the implicit ADI step above.
+ * theta = 1/2 (every member 2D): its Crank-Nicolson variant
+ *
+ *   (I + a D_x^2/2)(I + a D_y^2/2) C^{n+1}
+ *       = (I - a D_x^2/2)(I - a D_y^2/2) C^n + (RHS - C^n),   a = gamma dt,
+ *
+ * second order in dt where only the pure fourth derivatives act (paper:
+ * Appendix A, the scheme for hyper-diffusion alone) and first order once the
+ * explicit nonlinear and mixed terms act, as for theta = 1.  Its stiff axis
+ * modes are not damped: their growth factors approach -1 as gamma dt / h^4
+ * grows (about -0.99 for 512^2 grids at dt = 1e-3), where theta = 1 removes
+ * them within a step.  Applies from the next step; the state, the step
+ * counter and the series are kept; tile shapes are re-planned (the variant
+ * reads two halo lines on either side in y).  CH_EINVAL for any other theta,
+ * CH_EUNSUPPORTED if a member is 3D. */
+ch_status ch_set_theta(ch_ctx* ctx, double theta);
+
 /* Tile shapes.  ch_autotune times every valid tile shape of every size class
  * on the device (using the workspace's scratch field only: the state and the
  * series are untouched) and keeps the fastest.  With several classes it then

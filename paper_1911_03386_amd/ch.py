@@ -32,7 +32,7 @@ EXPORTED = (
     "ch_set_graph_steps", "ch_describe", "ch_time_kernels", "ch_destroy", "ch_last_error",
     "ch_version", "ch_solver_coefficients", "ch_num_classes", "ch_set_tiles",
     "ch_ensemble_moments", "ch_ensemble_window", "ch_beta_histogram", "ch_sync_step",
-    "ch_step_static",
+    "ch_step_static", "ch_set_theta",
 )
 
 # Allocation-free stepping (ch_step_static): limits of its static device scratch
@@ -101,6 +101,7 @@ def load() -> ctypes.CDLL:
         "ch_num_classes": (ctypes.c_int, [vp, P(ctypes.c_int32)]),
         "ch_set_tiles": (ctypes.c_int, [vp] + [ctypes.c_int32] * 9),
         "ch_sync_step": (ctypes.c_int, [vp, i64p]),
+        "ch_set_theta": (ctypes.c_int, [vp, ctypes.c_double]),
         "ch_step_static": (ctypes.c_int, [P(ch_member_desc), ctypes.c_int32, ctypes.c_int, vp,
                                           ctypes.c_int64, vp, vp]),
         "ch_ensemble_moments": (ctypes.c_int, [vp, P(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32, dp,
@@ -329,6 +330,10 @@ class Ensemble:
     def set_tiles(self, cls: int, cx: int, rl: int, waves: int, units: int, cy: int, by: int,
                   cz: int = 0, bz: int = 0):
         _check(load().ch_set_tiles(self.ctx, cls, cx, rl, waves, units, cy, by, cz, bz), self.ctx)
+
+    def set_theta(self, theta: float):
+        """Time scheme: 1 = implicit ADI (default), 0.5 = Crank-Nicolson ADI (2D)."""
+        _check(load().ch_set_theta(self.ctx, theta), self.ctx)
 
     def set_graph_steps(self, g: int):
         _check(load().ch_set_graph_steps(self.ctx, g), self.ctx)

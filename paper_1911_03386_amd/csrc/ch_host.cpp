@@ -52,6 +52,7 @@ struct ClassPlan {
     int dim = 2, nx = 0, ny = 0, nz = 1;
     std::vector<int> members;
     int nfixed = 0;  // member count of a plan built without a member list (ch_step_static)
+    bool cn = false; // Crank-Nicolson variant of the scheme (theta = 1/2; 2D)
     // pass A
     int cx = 0, rl = 1, waves = 4, units = 1, P = 0, rpw = 0, R = 0, bands = 0, pitch = 0;
     int64_t bpmA = 0;  // pass-A blocks per member
@@ -79,7 +80,7 @@ int lds_pos(int xx, int cx, int pad) { return xx + (xx / cx) * pad; }
 
 bool planA(ClassPlan& c, int prec, int cx, int rl, int waves, int units)
 {
-    if (!passA_has(c.dim, cx, rl, units) || c.nx % cx) return false;
+    if (!passA_has(c.dim, cx, rl, units, c.cn) || c.nx % cx) return false;
     const int P = c.nx / cx;
     if (P < 1 || P > 64) return false;
     if (waves < 1 || waves > kPassAThreads / 64) return false;
@@ -89,7 +90,7 @@ bool planA(ClassPlan& c, int prec, int cx, int rl, int waves, int units)
     if (cx % halo) return false;
     const int pitch = lds_pos(c.nx + 2 * halo - 1, cx, pad) + 1;
     const int planes = c.dim == 3 ? 4 : 1;
-    const size_t lds = (size_t)planes * (R + 3) * pitch * elem_size(prec);
+    const size_t lds = (size_t)planes * (R + (c.cn ? 4 : 3)) * pitch * elem_size(prec);
     if (lds > kLdsLimit) return false;
     if (units > 1) {
         // a wavefront's share of the plane a unit adds must fit the prefetch
@@ -414,6 +415,7 @@ void layout(const ch_member_desc* members, int32_t m, int prec, int64_t max_samp
 struct ch_ctx {
     std::vector<ch_member_desc> desc;
     int prec = 0, conv = 0, K = 10;
+    double theta = 1.0;  // 1: implicit ADI; 1/2: Crank-Nicolson ADI (2D)
     int64_t max_samples = 1;
     hipStream_t stream = nullptr;
     // streams of the other size classes (class ci runs on stream ci mod
@@ -475,7 +477,8 @@ ch_status fail(ch_ctx* ctx, ch_status st, const char* fmt, ...)
 
 // Device-table entry of one member: spacings, parameters and the line-solve
 // coefficients of every used axis for the chunk lengths of its class plan.
-void fill_member(const ch_member_desc& d, int64_t off, const ClassPlan& c, int prec, MemberDev& md)
+void fill_member(const ch_member_desc& d, int64_t off, const ClassPlan& c, int prec, double theta,
+                 MemberDev& md)
 {
     md = MemberDev{};
     md.off = off;
@@ -491,7 +494,7 @@ void fill_member(const ch_member_desc& d, int64_t off, const ClassPlan& c, int p
     md.dt = d.dt;
     for (int a = 0; a < d.dim; ++a) {
         const double h2 = md.h[a] * md.h[a];
-        const double rho = d.gamma * d.dt / (h2 * h2);
+        const double rho = theta * d.gamma * d.dt / (h2 * h2);  // the solves are (I + theta gamma dt D^2)
         const int chunk = a == 0 ? c.cx : c.col[a].cy;
         axis_coef(rho, d.n[a], chunk, prec, md.ax[a]);
     }
@@ -502,7 +505,8 @@ void fill_member_table(ch_ctx* ctx)
     const int m = (int)ctx->desc.size();
     ctx->mem.assign(m, MemberDev{});
     for (auto& c : ctx->classes)
-        for (int gi : c.members) fill_member(ctx->desc[gi], ctx->L.moff[gi], c, ctx->prec, ctx->mem[gi]);
+        for (int gi : c.members)
+            fill_member(ctx->desc[gi], ctx->L.moff[gi], c, ctx->prec, ctx->theta, ctx->mem[gi]);
 }
 
 ch_status upload_tables(ch_ctx* ctx)
@@ -542,6 +546,7 @@ PassAArgs passA_args(ch_ctx* ctx, int ci, int mode)
     a.mode = mode;
     a.conv = ctx->conv;
     a.K = ctx->K;
+    a.cn = c.cn ? 1 : 0;
     a.step = ctx->d_steps() + ci;
     a.partials = reinterpret_cast<double*>(ctx->ws + c.off_partials);
     a.nstamp = ctx->d_nstamp() + ci;
@@ -759,8 +764,8 @@ std::string plan_text(const ch_ctx* ctx)
     char buf[320];
     for (const auto& c : ctx->classes) {
         snprintf(buf, sizeof buf,
-                 "%dD %dx%dx%d %s x%zu: A cx=%d rl=%d P=%d waves=%d units=%d R=%d blocks=%lld lds=%zu",
-                 c.dim, c.nx, c.ny, c.nz, ctx->prec ? "f32" : "f64", c.members.size(), c.cx, c.rl, c.P,
+                 "%dD %dx%dx%d %s%s x%zu: A cx=%d rl=%d P=%d waves=%d units=%d R=%d blocks=%lld lds=%zu",
+                 c.dim, c.nx, c.ny, c.nz, ctx->prec ? "f32" : "f64", c.cn ? " cn" : "", c.members.size(), c.cx, c.rl, c.P,
                  c.waves, c.units, c.R, (long long)c.nblocksA, c.ldsA);
         s += buf;
         for (int a = 1; a < c.dim; ++a) {
@@ -776,8 +781,8 @@ std::string plan_text(const ch_ctx* ctx)
 std::string class_key(const ch_ctx* ctx, const ClassPlan& c)
 {
     char buf[128];
-    snprintf(buf, sizeof buf, "%s:%s:%dD:%dx%dx%d:m%zu", ctx->arch.c_str(), ctx->prec ? "f32" : "f64",
-             c.dim, c.nx, c.ny, c.nz, c.members.size());
+    snprintf(buf, sizeof buf, "%s:%s:%dD:%dx%dx%d:m%zu%s", ctx->arch.c_str(), ctx->prec ? "f32" : "f64",
+             c.dim, c.nx, c.ny, c.nz, c.members.size(), c.cn ? ":cn" : "");
     return buf;
 }
 
@@ -1216,6 +1221,30 @@ ch_status ch_set_graph_steps(ch_ctx* ctx, int32_t graph_steps)
     if (graph_steps > 0 && ctx->stream != nullptr && cap == hipStreamCaptureStatusNone)
         return ensure_graph(ctx, graph_steps);
     return CH_OK;
+}
+
+ch_status ch_set_theta(ch_ctx* ctx, double theta)
+{
+    ch_status st = check_ctx(ctx);
+    if (st != CH_OK) return st;
+    if (theta != 1.0 && theta != 0.5) return fail(ctx, CH_EINVAL, "theta must be 1 or 1/2");
+    const bool cn = theta == 0.5;
+    std::vector<ClassPlan> plans = ctx->classes;
+    for (auto& c : plans) {
+        if (cn && c.dim != 2)
+            return fail(ctx, CH_EUNSUPPORTED, "the Crank-Nicolson variant needs 2D members only");
+        c.cn = cn;
+        // keep the class's shape where it is valid for the new variant
+        if (!planA(c, ctx->prec, c.cx, c.rl, c.waves, c.units) && !default_A(c, ctx->prec))
+            return fail(ctx, CH_EUNSUPPORTED, "no tile shape fits a size class in LDS");
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->classes = plans;
+    ctx->theta = theta;
+    fill_member_table(ctx);
+    st = upload_tables(ctx);
+    drop_graph(ctx);
+    return st;
 }
 
 ch_status ch_describe(const ch_ctx* ctx, char* buf, size_t cap)
@@ -1692,7 +1721,7 @@ ch_status ch_step_static(const ch_member_desc* members, int32_t m, ch_precision 
     }
     char* base = static_cast<char*>(g_static_ptr[dev]);
     for (int i = 0; i < m; ++i) {
-        fill_member(members[i], (int64_t)i * sites, c, prec, g_static_mem[i]);
+        fill_member(members[i], (int64_t)i * sites, c, prec, 1.0, g_static_mem[i]);
         g_static_mids[i] = i;
     }
     // pageable host-to-device copies: the staging tables are read before the

