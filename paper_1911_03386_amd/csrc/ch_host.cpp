@@ -45,7 +45,7 @@ size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 
 struct ColPlan {
     int cy = 0, b = 0, P = 0;
-    int64_t cols = 0, stride = 0, outer = 0, nblocks = 0;
+    int64_t cols = 0, stride = 0, run = 0, outer = 0, nblocks = 0;
 };
 
 struct ClassPlan {
@@ -128,10 +128,11 @@ bool planCol(ClassPlan& c, int prec, int axis, int cy, int b)
     // a block's b columns must be contiguous in memory: y-lines (and 2D) run
     // along x only, z-lines along the whole x-y plane
     const int64_t run = axis == 1 ? c.nx : (int64_t)c.nx * c.ny;
-    if (b < 1 || run % b || b * P > kColMaxThreads) return false;
+    if (b < 1 || (b & (b - 1)) || run % b || b * P > kColMaxThreads) return false;
     p.cy = cy;
     p.b = b;
     p.P = P;
+    p.run = run;
     if (axis == 1) {
         p.stride = c.nx;
         p.cols = (int64_t)c.nx * c.nz;
@@ -139,7 +140,7 @@ bool planCol(ClassPlan& c, int prec, int axis, int cy, int b)
     } else {
         p.stride = (int64_t)c.nx * c.ny;
         p.cols = (int64_t)c.nx * c.ny;
-        p.outer = c.nx;
+        p.outer = run;
     }
     p.nblocks = class_size(c) * (p.cols / b);
     return true;
@@ -587,10 +588,11 @@ ColArgs col_args(ch_ctx* ctx, int ci, int axis, const void* src, void* dst, bool
     a.axis = axis;
     a.n = axis == 1 ? c.ny : c.nz;
     a.stride = p.stride;
-    a.nx = c.nx;
+    a.run = p.run;
     a.outer = p.outer;
     a.cols = p.cols;
     a.b = p.b;
+    a.bshift = __builtin_ctz((unsigned)p.b);
     a.P = p.P;
     a.nblocks = p.nblocks;
     if (closes_step) {
@@ -1789,10 +1791,11 @@ ch_status ch_step_static(const ch_member_desc* members, int32_t m, ch_precision 
         ca.axis = axis;
         ca.n = axis == 1 ? c.ny : c.nz;
         ca.stride = p.stride;
-        ca.nx = c.nx;
+        ca.run = p.run;
         ca.outer = p.outer;
         ca.cols = p.cols;
         ca.b = p.b;
+        ca.bshift = __builtin_ctz((unsigned)p.b);
         ca.P = p.P;
         ca.nblocks = p.nblocks;
         if (last) {

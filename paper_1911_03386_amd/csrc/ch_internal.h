@@ -103,10 +103,11 @@ struct ColArgs {
     int32_t axis;              // 1 = y, 2 = z
     int32_t n;                 // line length
     int64_t stride;            // element distance between line neighbours
-    int32_t nx;                // columns come in runs of nx consecutive elements
+    int64_t run;               // columns come in runs of `run` consecutive elements
     int64_t outer;             // element distance between runs
     int64_t cols;              // columns per member
-    int32_t b;                 // columns per block (divides nx)
+    int32_t b;                 // columns per block (a power of two dividing run)
+    int32_t bshift;            // log2 b
     int32_t P;                 // chunks per column
     int64_t nblocks;
     FinArgs fin;               // enabled on the last sweep of a step

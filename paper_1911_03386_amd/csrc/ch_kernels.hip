@@ -69,6 +69,37 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// Raw buffer access: a buffer resource (base address and byte range in
+// scalar registers) plus a 32-bit per-lane byte offset and a wave-uniform
+// scalar byte offset, so that strided accesses need no per-lane 64-bit
+// address arithmetic; accesses past the range read 0 and write nothing.
+// (The third resource word is the gfx9-family raw-buffer format.)
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+
 template <typename T>
 struct LineCoef {
     T a1, a2, ik;
@@ -1232,29 +1263,42 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
     const int P = a.P;
     // blockDim.x is b * P rounded up to whole wavefronts; threads beyond b * P
     // only take part in the barriers
-    const int j0 = tid / a.b;
+    const int j0 = tid >> a.bshift;  // b is a power of two
     const bool colok = j0 < P;
     const int j = colok ? j0 : 0;
-    const int c = tid - j0 * a.b;
+    const int c = tid & (a.b - 1);
     const int64_t blk = xcd_remap(blockIdx.x, a.nblocks);
-    const int64_t bpm = a.cols / a.b;
+    const int64_t bpm = a.cols >> a.bshift;
     const int mloc = (int)(blk / bpm);
-    const int64_t col = (blk - (int64_t)mloc * bpm) * a.b + c;
-    const int64_t base = (col % a.nx) + (col / a.nx) * a.outer;
+    // the block's b columns are consecutive elements of one run (b divides the
+    // run length): its first column's element offset is block-uniform
+    const int64_t col0 = (blk - (int64_t)mloc * bpm) << a.bshift;
+    const int64_t run = col0 / a.run;
+    const int64_t base0 = (col0 - run * a.run) + run * a.outer;
     const MemberDev& md = a.mem[a.mids[mloc]];
-    const T* src = reinterpret_cast<const T*>(a.src) + md.off + base;
-    T* dst = reinterpret_cast<T*>(a.dst) + md.off + base;
     const int64_t st = a.stride;
+    // lane offset: column c, first element of chunk j; element k of the chunk
+    // adds the uniform k * stride
+    const uint32_t span = (uint32_t)((md.sites - base0) * (int64_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rsrc = buffer_of(reinterpret_cast<const T*>(a.src) + md.off + base0, span);
+    const __amdgpu_buffer_rsrc_t rdst = buffer_of(reinterpret_cast<T*>(a.dst) + md.off + base0, span);
+    const int voff = (int)(((int64_t)j * CY * st + c) * (int64_t)sizeof(T));
+    const int sstep = (int)(st * (int64_t)sizeof(T));
 
     T v[CY];
 #pragma unroll
-    for (int k = 0; k < CY; ++k) v[k] = colok ? src[(int64_t)(j * CY + k) * st] : T(0);
+    for (int k = 0; k < CY; ++k) v[k] = colok ? buf_load<T>(rsrc, voff, k * sstep) : T(0);
 
     const AxisCoef& ac = md.ax[a.axis];
     const T a1 = (T)ac.a1, a2 = (T)ac.a2, ik = (T)ac.ikappa;
-    T W[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) W[i] = (T)ac.W[i];
+    // the scan's 2x2 matrices live in LDS (read as broadcasts where they are
+    // used), which keeps them out of the scalar registers
+    __shared__ T sco[(kMaxScanLevels + 1) * 4];  // Mp[0..6], then W
+    if (tid < kMaxScanLevels * 4)
+        sco[tid] = (T)ac.Mp[tid >> 2][tid & 3];
+    else if (tid < (kMaxScanLevels + 1) * 4)
+        sco[tid] = (T)ac.W[tid - kMaxScanLevels * 4];
+    const T* W = sco + kMaxScanLevels * 4;
 
     // causal recursion.  The line mean m passes through the solve unchanged;
     // the recursions run on v - m (chunk end states corrected by m * E1, the
@@ -1265,11 +1309,7 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
     // level) with the powers M^(2^s) of the chunk transfer matrix; the ring is
     // closed with (I - A^n)^{-1} as in the x-solve.
     const T E10 = (T)ac.E1[0], E11 = (T)ac.E1[1];
-    T Mp[kMaxScanLevels][4];
-#pragma unroll
-    for (int l = 0; l < kMaxScanLevels; ++l)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) Mp[l][i] = (T)ac.Mp[l][i];
+    auto Mp = [&](int l) -> const T* { return sco + 4 * l; };
     T e0, e1, csum = T(0);
 #pragma unroll
     for (int k = 0; k < CY; ++k) csum += v[k];
@@ -1299,7 +1339,7 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
         __syncthreads();
         if (colok && j >= d) {
             T y0 = B0(pp)[me - d * a.b], y1 = B1(pp)[me - d * a.b];
-            mv(Mp[l], y0, y1);
+            mv(Mp(l), y0, y1);
             e0 += y0;
             e1 += y1;
         }
@@ -1316,7 +1356,7 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
         T r0 = W[0] * z0 + W[1] * z1, r1 = W[2] * z0 + W[3] * z1;
 #pragma unroll
         for (int l = 0; l < kMaxScanLevels; ++l)
-            if (((1 << l) < P) && (j & (1 << l))) mv(Mp[l], r0, r1);
+            if (((1 << l) < P) && (j & (1 << l))) mv(Mp(l), r0, r1);
         if (j > 0) {
             r0 += B0(pp)[me - a.b];
             r1 += B1(pp)[me - a.b];
@@ -1340,7 +1380,7 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
         __syncthreads();
         if (colok && jr >= d) {
             T y0 = B0(pp)[me + d * a.b], y1 = B1(pp)[me + d * a.b];
-            mv(Mp[l], y0, y1);
+            mv(Mp(l), y0, y1);
             e0 += y0;
             e1 += y1;
         }
@@ -1357,7 +1397,7 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
         T r0 = W[0] * z0 + W[1] * z1, r1 = W[2] * z0 + W[3] * z1;
 #pragma unroll
         for (int l = 0; l < kMaxScanLevels; ++l)
-            if (((1 << l) < P) && (jr & (1 << l))) mv(Mp[l], r0, r1);
+            if (((1 << l) < P) && (jr & (1 << l))) mv(Mp(l), r0, r1);
         if (j < P - 1) {
             r0 += B0(pp)[me + a.b];
             r1 += B1(pp)[me + a.b];
@@ -1367,7 +1407,7 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
 
     if (colok)
 #pragma unroll
-        for (int k = 0; k < CY; ++k) dst[(int64_t)(j * CY + k) * st] = v[k];
+        for (int k = 0; k < CY; ++k) buf_store(v[k], rdst, voff, k * sstep);
 
     // last sweep of the step: the first G blocks reduce the pass-A partials (pass
     // A ran to completion before this launch) and one thread advances the step
