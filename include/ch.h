@@ -60,7 +60,16 @@ extern "C" {
 
 typedef struct ch_ctx ch_ctx; /* opaque */
 
-typedef enum {
+/* The enums are int-sized, and any int may be passed for them: the library
+ * checks the values (in C++ the fixed underlying type makes every int a
+ * valid value of the type). */
+#ifdef __cplusplus
+#define CH_ENUM_INT : int
+#else
+#define CH_ENUM_INT
+#endif
+
+typedef enum CH_ENUM_INT {
     CH_OK = 0,
     CH_EINVAL = 1,       /* bad argument; nothing was enqueued */
     CH_ENOMEM = 2,       /* workspace too small, or host allocation failed */
@@ -71,13 +80,13 @@ typedef enum {
     CH_EUNSUPPORTED = 6  /* valid but unsupported shape (see ch_member_desc) */
 } ch_status;
 
-typedef enum {
+typedef enum CH_ENUM_INT {
     CH_F64 = 0,      /* state, stencils and line solves in FP64 */
     CH_F32_BULK = 1  /* state, stencils and line solves in FP32; F, <C>, G and
                         beta are always reduced and reported in FP64 */
 } ch_precision;
 
-typedef enum {
+typedef enum CH_ENUM_INT {
     CH_ENERGY_QUARTER = 0,       /* e(C) = (C^2-1)^2/4, consistent with eq. (ch) */
     CH_ENERGY_PAPER_PRINTED = 1  /* e(C) = (C^2-1)^2/2, the prefactor printed
                                     with eq. (dFdt_ch) */

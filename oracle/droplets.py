@@ -35,6 +35,21 @@ eq. (betaN)):
 
 Sums over droplets inside a step use numpy's pairwise sum; the sample
 diagnostics use exactly rounded sums (math.fsum).
+
+The radius form (Section 3.1 as printed) is here too, for the comparison with
+the paper's own runs: the state is R itself and
+
+    dR_i/dt = H(R_i + eps) (-1/R_i^2 + ubar/R_i),  ubar over the R_i > 0,
+
+eps = 1e-3: a droplet that crosses R = 0 leaves the mean field and the
+energy at once and keeps moving (ever faster) until R <= -eps, where it
+stops.  The rate is singular at R = 0, so an integrator has to shrink its
+step there; with the max norm above it cannot pass the first death (the step
+underflows), while the root-mean-square norm
+    err = sqrt(mean_i (|h sum_s e_s k_{s,i}| / (atol + rtol max(|R_i|, |R_i^new|)))^2)
+(Hairer, Norsett and Wanner's choice) dilutes one droplet's error over the
+population and lets loose tolerances through.  The same integrator serves
+both forms (`norm` selects the error norm).
 """
 from __future__ import annotations
 
@@ -87,12 +102,15 @@ def _step_factor(err: float) -> float:
 
 
 def dp45(f, y0, t_end: float, dts: float, rtol: float, atol: float, h0: float,
-         max_attempts: int = 10**7, on_sample=None, fixed_h: float | None = None):
+         max_attempts: int = 10**7, on_sample=None, fixed_h: float | None = None, norm: str = "max"):
     """Integrate y' = f(y) (autonomous, vector y) from t = 0 with the
     Dormand-Prince pair and the error control above.  Samples at t_j = j dts,
     j = 0..J-1 with J = round(t_end/dts) + 1: on_sample(j, t_j, y) is called
     on each (also j = 0).  With fixed_h, every step is accepted with that
-    size (sample clipping still applies).  Returns (y, accepted, rejected)."""
+    size (sample clipping still applies).  norm: "max" (the default, as
+    ode45) or "rms" over the components.  Returns (y, accepted, rejected)."""
+    if norm not in ("max", "rms"):
+        raise ValueError(norm)
     A, b5, _, _, e = tableau()
     J = int(round(t_end / dts)) + 1
     y = np.array(y0, dtype=np.float64)
@@ -122,7 +140,13 @@ def dp45(f, y0, t_end: float, dts: float, rtol: float, atol: float, h0: float,
         for j in range(7):
             est = est + e[j] * k[j]
         sc = atol + rtol * np.maximum(np.abs(y), np.abs(y5))
-        err = float(np.max(np.abs(h * est) / sc)) if y.size else 0.0
+        q = np.abs(h * est) / sc
+        if not y.size:
+            err = 0.0
+        elif norm == "max":
+            err = float(np.max(q))
+        else:
+            err = math.sqrt(float(np.mean(q * q)))
         if not math.isfinite(err):
             raise FloatingPointError("non-finite error estimate")
         if fixed_h is not None:
@@ -178,10 +202,7 @@ def rate(V: np.ndarray) -> np.ndarray:
     return np.where(alive, 3.0 * (ubar * R - 1.0), 0.0)
 
 
-def diagnostics(t: float, V: np.ndarray):
-    """(t, F, dF/dt, beta, ubar, alive) of a state, exactly rounded sums."""
-    alive = V > 0.0
-    R = [float(r) for r in np.cbrt(V[alive])]
+def _diagnostics_of_radii(t: float, R):
     n = len(R)
     if n == 0:
         return (t, 0.0, 0.0, math.nan, 0.0, 0.0)
@@ -190,6 +211,12 @@ def diagnostics(t: float, V: np.ndarray):
     dF = -math.fsum((1.0 - ubar * r) ** 2 / r for r in R)
     beta = 0.0 if t == 0.0 else -t * dF / F
     return (t, F, dF, beta, ubar, float(n))
+
+
+def diagnostics(t: float, V: np.ndarray):
+    """(t, F, dF/dt, beta, ubar, alive) of a state, exactly rounded sums."""
+    alive = V > 0.0
+    return _diagnostics_of_radii(t, [float(r) for r in np.cbrt(V[alive])])
 
 
 def run_member(R0, t_end: float, dts: float = 0.1, rtol: float = 1e-6, atol: float = 1e-9,
@@ -204,3 +231,57 @@ def run_member(R0, t_end: float, dts: float = 0.1, rtol: float = 1e-6, atol: flo
 
     V, acc, rej = dp45(rate, volumes_from_radii(R0), t_end, dts, rtol, atol, h0, max_attempts, rec)
     return series, V, acc, rej
+
+
+# --------------------------------------------------------------------------
+# The radius form of Section 3.1 (the paper's own numerics)
+# --------------------------------------------------------------------------
+EPS_RADIUS = 1e-3  # the paper's eps
+
+
+def rate_radius(R: np.ndarray, eps: float = EPS_RADIUS) -> np.ndarray:
+    """dR/dt = H(R + eps) (-1/R^2 + ubar/R) with ubar = sum H(R) / sum H(R) R
+    (eq. (uval)); 0 where R <= -eps."""
+    alive = R > 0.0
+    cnt = int(np.count_nonzero(alive))
+    ubar = cnt / float(np.sum(R[alive])) if cnt else 0.0
+    moving = R > -eps
+    Rs = np.where(moving & (R != 0.0), R, 1.0)
+    return np.where(moving & (R != 0.0), -1.0 / (Rs * Rs) + ubar / Rs, np.where(moving, -np.inf, 0.0))
+
+
+def diagnostics_radius(t: float, R: np.ndarray):
+    """(t, F, dF/dt, beta, ubar, alive) of a radius state: the droplets with
+    R > 0 (H(R)), eq. (Fdef), eq. (dFdt), eq. (betaN); exactly rounded sums."""
+    return _diagnostics_of_radii(t, [float(r) for r in R[R > 0.0]])
+
+
+def run_member_radius(R0, t_end: float, dts: float = 0.1, rtol: float = 1e-3, atol: float = 1e-6,
+                      h0: float = 1e-4, eps: float = EPS_RADIUS, norm: str = "rms",
+                      max_attempts: int = 10**7):
+    """One member in the radius form: returns (series (J, 6) in SLOTS order,
+    final R, accepted, rejected).  Raises FloatingPointError when the step
+    size underflows (at a death, for tight tolerances or the max norm)."""
+    J = int(round(t_end / dts)) + 1
+    series = np.full((J, len(SLOTS)), np.nan)
+
+    def rec(j, t, y):
+        series[j] = diagnostics_radius(t, y)
+
+    R, acc, rej = dp45(lambda y: rate_radius(y, eps), np.array(R0, dtype=np.float64), t_end, dts, rtol, atol,
+                       h0, max_attempts, rec, norm=norm)
+    return series, R, acc, rej
+
+
+def beta_from_F_differences(series: np.ndarray) -> np.ndarray:
+    """beta_j = -t_j (F_{j+1} - F_{j-1}) / ((t_{j+1} - t_{j-1}) F_j) from the
+    sampled F (one-sided at the ends; 0 at t = 0): the coarsening rate of
+    eq. (betaN) with dF/dt taken from the output grid."""
+    t, F = series[:, 0], series[:, 1]
+    dF = np.empty_like(F)
+    dF[1:-1] = (F[2:] - F[:-2]) / (t[2:] - t[:-2])
+    dF[0] = (F[1] - F[0]) / (t[1] - t[0])
+    dF[-1] = (F[-1] - F[-2]) / (t[-1] - t[-2])
+    beta = -t * dF / F
+    beta[0] = 0.0
+    return beta

@@ -193,3 +193,64 @@ def test_dFdt_matches_difference_of_F():
     fd = (s[2:, 1] - s[:-2, 1]) / (2e-3)
     rel = np.abs(fd - s[1:-1, 2]) / np.abs(s[1:-1, 2])
     assert np.max(rel) < 1e-5, np.max(rel)
+
+
+# --------------------------------------------------------------------------
+# The radius form of Section 3.1 against the volume form
+# --------------------------------------------------------------------------
+def test_radius_form_matches_volume_form_before_first_death():
+    """Where both are defined (before any droplet reaches R = 0) the radius
+    form dR/dt = -1/R^2 + ubar/R and the volume form dV/dt = 3 (ubar R - 1)
+    are the same law: at tight tolerances their series and states agree to
+    the integrators' error."""
+    rng = np.random.default_rng(11)
+    R0 = rng.uniform(0.45, 1.0, 32)
+    s, _, _, _ = D.run_member(R0, 1.0, dts=0.01, rtol=1e-11, atol=1e-14)
+    t_death = s[np.argmax(s[:, 5] < 32), 0]
+    assert 0.05 < t_death < 1.0
+    T = 0.8 * t_death
+    sv, V, _, _ = D.run_member(R0, T, dts=T / 20, rtol=1e-11, atol=1e-14)
+    sr, R, _, _ = D.run_member_radius(R0, T, dts=T / 20, rtol=1e-11, atol=1e-14, norm="max")
+    assert np.all(sr[:, 5] == 32) and np.all(sv[:, 5] == 32)
+    for col in (1, 2, 4):
+        assert np.abs(sr[:, col] - sv[:, col]).max() <= 1e-9 * np.abs(sv[:, col]).max(), col
+    assert np.abs(sr[1:, 3] - sv[1:, 3]).max() <= 1e-8
+    assert np.abs(R - np.cbrt(V)).max() <= 1e-9
+
+
+def test_radius_form_death_and_regularisation():
+    """A droplet that reaches R = 0 leaves the mean field and the energy at
+    the same sample as in the volume form, then runs on to R <= -eps and
+    stops; F of the two forms agrees to the loose tolerance's error."""
+    R0 = np.array([0.5, 0.9, 1.0])
+    sv, V, _, _ = D.run_member(R0, 1.0, dts=0.01, rtol=1e-11, atol=1e-14)
+    sr, R, _, _ = D.run_member_radius(R0, 1.0, dts=0.01, rtol=1e-3, atol=1e-6, norm="rms")
+    np.testing.assert_array_equal(sr[:, 5], sv[:, 5])
+    assert sv[-1, 5] == 2.0 and V[0] <= 0.0
+    assert R[0] <= -D.EPS_RADIUS and R[1] > 0 and R[2] > 0
+    assert np.abs(sr[:, 1] - sv[:, 1]).max() <= 1e-5 * sv[0, 1]
+    # after the death the diagnostics see the two live droplets only
+    assert sr[-1, 1] == pytest.approx(0.5 * (R[1] ** 2 + R[2] ** 2), rel=1e-15)
+
+
+def test_radius_form_needs_the_rms_norm():
+    """With ode45's max norm the singular rate at R = 0 stops the integration
+    at the first death of a U(0, 1) population (the step size underflows);
+    the root-mean-square norm passes it at rtol 1e-3 but not at 1e-5."""
+    R0 = np.random.default_rng(123).uniform(0.0, 1.0, 64)
+    with pytest.raises(FloatingPointError):
+        D.run_member_radius(R0, 40.0, rtol=1e-3, atol=1e-6, norm="max")
+    s, _, _, _ = D.run_member_radius(R0, 40.0, rtol=1e-3, atol=1e-6, norm="rms")
+    assert np.all(np.isfinite(s[:, 1])) and s[-1, 5] >= 1
+    with pytest.raises(FloatingPointError):
+        D.run_member_radius(R0, 40.0, rtol=1e-5, atol=1e-8, norm="rms")
+
+
+def test_beta_from_F_differences_definition():
+    t = np.linspace(0.0, 1.0, 11)
+    F = 2.0 * (1.0 + t) ** -0.5  # beta = t / (2 (1 + t)) exactly for this F
+    s = np.zeros((11, 6))
+    s[:, 0], s[:, 1] = t, F
+    b = D.beta_from_F_differences(s)
+    exact = t / (2.0 * (1.0 + t))
+    assert b[0] == 0.0 and np.abs(b[1:-1] - exact[1:-1]).max() < 2e-3
