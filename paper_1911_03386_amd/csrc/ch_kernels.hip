@@ -99,6 +99,18 @@ __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, in
 {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
 }
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// 16-byte vectors (float4 / double2)
+template <typename VT>
+__device__ __forceinline__ VT buf_load16(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+template <typename VT>
+__device__ __forceinline__ void buf_store16(const VT& v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
+}
 
 template <typename T>
 struct LineCoef {
@@ -454,7 +466,7 @@ struct PadOf<float> {
 template <typename T, int CX, int RL>
 __device__ __forceinline__ void write_back(T* so, int pitch, const T (&v)[RL][CX], const bool (&rowok)[RL],
                                            int rl0, int j, int wv, int lane, int rpw, int Ract, int nvec,
-                                           T* out, int nx)
+                                           __amdgpu_buffer_rsrc_t rout, int out0, int nx)
 {
     constexpr int PADE = PadOf<T>::v;
     constexpr int VEC = Vec16<T>::n;
@@ -479,12 +491,12 @@ __device__ __forceinline__ void write_back(T* so, int pitch, const T (&v)[RL][CX
     int l = wv * rpw, seg = 0;  // wave-uniform cursor (line, segment)
     while (l < l1) {
         VT val[NB];
-        T* row[NB];
+        int row[NB];  // element offset of the line in the output (wave-uniform)
         int off[NB];
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             off[i] = -1;
-            row[i] = out + (int64_t)l * nx;
+            row[i] = out0 + l * nx;
             if (l < l1) {
                 const int xv = seg * 64 + lane;
                 if (xv < nvec) {
@@ -500,7 +512,7 @@ __device__ __forceinline__ void write_back(T* so, int pitch, const T (&v)[RL][CX
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i)
-            if (off[i] >= 0) *reinterpret_cast<VT*>(row[i] + (uint32_t)off[i]) = val[i];
+            if (off[i] >= 0) buf_store16<VT>(val[i], rout, off[i] * (int)sizeof(T), row[i] * (int)sizeof(T));
     }
 }
 
@@ -585,6 +597,8 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     const MemberDev& md = a.mem[mid];
     const T* C = reinterpret_cast<const T*>(a.C) + md.off;
     T* Wout = reinterpret_cast<T*>(a.W) + md.off;
+    // the member's field as a buffer: rows are wave-uniform scalar offsets
+    const __amdgpu_buffer_rsrc_t rC = buffer_of(C, (uint32_t)(md.sites * (int64_t)sizeof(T)));
 
     const int64_t n = *a.step;
     const int K = a.K;
@@ -634,11 +648,11 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
                 if (pl < npl) {
                     const int zz = (DIM == 3) ? wrapi(z - 1 + pl, nz) : 0;
                     const int yy = wrapi(y0 - YLO + r, ny);
-                    const T* row = C + ((int64_t)zz * ny + yy) * nx;
+                    const int rowo = (zz * ny + yy) * nx;  // wave-uniform
                     const int xi = seg * 64 + lane;
                     if (xi < nvec) {
                         const uint32_t xs = (uint32_t)xi * VEC, xx = xs + HALO;
-                        val[i] = *reinterpret_cast<const VT*>(row + xs);
+                        val[i] = buf_load16<VT>(rC, (int)xs * (int)sizeof(T), rowo * (int)sizeof(T));
                         dst[i] = pl * planeStride + r * pitch + (int)(xx + xx / CX * PADE);
                     }
                     if (++seg == nseg) {
@@ -667,7 +681,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
             // left halo: the last vector of the row; right halo: the first
             const int xs = (h & 1) ? 0 : nx - HALO;
             const int xx = (h & 1) ? nx + HALO : 0;
-            const VT val = *reinterpret_cast<const VT*>(C + ((int64_t)zz * ny + yy) * nx + xs);
+            const VT val = buf_load16<VT>(rC, ((zz * ny + yy) * nx + xs) * (int)sizeof(T), 0);
             T e[VEC];
             vec_get<T>(val, e);
             const int d = pl * planeStride + r * pitch + xx + (xx / CX) * PADE;
@@ -854,7 +868,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     // (the __syncthreads above ended every read of the staged rows)
     if (solve)
         write_back<T, CX, RL>(sC + pitch, pitch, v, rowok, rl0, j, wv, lane, a.rows_per_wave, Ract, nvec,
-                              Wout + ((int64_t)z * ny + y0) * nx, nx);
+                              buffer_of(Wout, (uint32_t)(md.sites * (int64_t)sizeof(T))), (z * ny + y0) * nx, nx);
 
     // ---- block partials of F, sum C, sum |grad mu|^2 (reduced by finalize) ----
     if (blk == 0 && tid == 0 && a.mode != MODE_TIMING) *a.nstamp = n;
@@ -1187,7 +1201,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_multi_kernel(PassAArgs a)
         if (DIM == 2 && solve) {
             __syncthreads();  // every read of the staged rows is done
             write_back<T, CX, RL>(sC + pitch, pitch, v, rowok, rl0, j, wv, lane, a.rows_per_wave, Ract, nvec,
-                                  Wout + (int64_t)y0 * nx, nx);
+                                  buffer_of(Wout, (uint32_t)(md.sites * (int64_t)sizeof(T))), y0 * nx, nx);
         }
 
         if (has_next) {
