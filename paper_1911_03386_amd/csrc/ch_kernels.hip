@@ -46,6 +46,7 @@
 // chunk then reruns the recursion from its true incoming state.  Work per
 // element and sweep: four two-term recursions and one scale.
 #include "ch_internal.h"
+#include "ensemble_stats.h"
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -519,35 +520,34 @@ __device__ __forceinline__ void write_back(T* so, int pitch, const T (&v)[RL][CX
 
 // RHS of the scheme at line q, element m of a lane's staged rows:
 //   C + dt lap_h(C^3 - C) - 2 gamma dt sum_{d<e} D_d D_e C
+// with the coefficients folded: dx = dt / h_x^2 (etc.) and
+// gxy = 2 gamma dt / (h_x^2 h_y^2) (etc.), so that each second difference
+// costs one add and one fma and enters with one fma.
 // `at(dz, dy, m)` reads the staged field.  A mixed term D_d D_e C is formed
 // as the d-second difference of e-second differences; the inner differences
 // and the values of C^3 - C at neighbouring sites are the same expressions a
 // neighbouring element or line of the lane forms, so the unrolled loops
 // compute each of them once.
 template <typename T, int DIM, typename At>
-__device__ __forceinline__ T rhs_site(const At& at, int q, int m, T ihx2, T ihy2, T ihz2, T dt, T tg,
-                                      T cxy, T cxz, T cyz)
+__device__ __forceinline__ T rhs_site(const At& at, int q, int m, T dx, T dy, T dz, T gxy, T gxz, T gyz)
 {
     auto N = [](T c) { return c * c * c - c; };
-    auto dyy = [&](int dz, int mm) {
-        return at(dz, q + 1, mm) + at(dz, q - 1, mm) - T(2) * at(dz, q, mm);
-    };
+    auto d2 = [](T a, T b, T c) { return fma(T(-2), b, a + c); };  // a - 2 b + c
+    auto dyy = [&](int dzz, int mm) { return d2(at(dzz, q + 1, mm), at(dzz, q, mm), at(dzz, q - 1, mm)); };
     const T c = at(0, q, m);
     const T Nc = N(c);
-    T lapN = (N(at(0, q, m + 1)) + N(at(0, q, m - 1)) - T(2) * Nc) * ihx2 +
-             (N(at(0, q + 1, m)) + N(at(0, q - 1, m)) - T(2) * Nc) * ihy2;
-    const T dy0 = dyy(0, m);
-    T cross = (dyy(0, m + 1) + dyy(0, m - 1) - T(2) * dy0) * cxy;
+    T r = fma(dx, d2(N(at(0, q, m + 1)), Nc, N(at(0, q, m - 1))), c);
+    r = fma(dy, d2(N(at(0, q + 1, m)), Nc, N(at(0, q - 1, m))), r);
+    r = fma(-gxy, d2(dyy(0, m + 1), dyy(0, m), dyy(0, m - 1)), r);
     if (DIM == 3) {
-        auto dzz = [&](int dy, int mm) {
-            return at(1, q + dy, mm) + at(-1, q + dy, mm) - T(2) * at(0, q + dy, mm);
+        auto dzz = [&](int ddy, int mm) {
+            return d2(at(1, q + ddy, mm), at(0, q + ddy, mm), at(-1, q + ddy, mm));
         };
-        lapN += (N(at(1, q, m)) + N(at(-1, q, m)) - T(2) * Nc) * ihz2;
-        const T dz0 = dzz(0, m);
-        cross += (dzz(0, m + 1) + dzz(0, m - 1) - T(2) * dz0) * cxz;
-        cross += (dzz(1, m) + dzz(-1, m) - T(2) * dz0) * cyz;
+        r = fma(dz, d2(N(at(1, q, m)), Nc, N(at(-1, q, m))), r);
+        r = fma(-gxz, d2(dzz(0, m + 1), dzz(0, m), dzz(0, m - 1)), r);
+        r = fma(-gyz, d2(dzz(1, m), dzz(0, m), dzz(-1, m)), r);
     }
-    return c + dt * lapN - tg * cross;
+    return r;
 }
 
 
@@ -709,10 +709,14 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     const T* cb = sC + PL0 * planeStride + (rl0 + YLO) * pitch + j * (CX + PADE);
 #define AT(dz, dy, m) cb[(dz) * planeStride + (dy) * pitch + (m) + ((m) / CX) * PADE]
 
-    const T ihx2 = (T)md.ih2[0], ihy2 = (T)md.ih2[1], ihz2 = (T)md.ih2[2];
+    const T ihx2 = (T)md.ih2[0], ihy2 = (T)md.ih2[1];
     const T dt = (T)md.dt, tg = (T)(2.0 * md.gamma * md.dt);
     const T cxy = (T)(md.ih2[0] * md.ih2[1]);
-    const T cxz = (T)(md.ih2[0] * md.ih2[2]), cyz = (T)(md.ih2[1] * md.ih2[2]);
+    // folded coefficients of the RHS
+    const T cdx = (T)(md.dt * md.ih2[0]), cdy = (T)(md.dt * md.ih2[1]), cdz = (T)(md.dt * md.ih2[2]);
+    const T gxy = (T)(2.0 * md.gamma * md.dt * md.ih2[0] * md.ih2[1]);
+    const T gxz = (T)(2.0 * md.gamma * md.dt * md.ih2[0] * md.ih2[2]);
+    const T gyz = (T)(2.0 * md.gamma * md.dt * md.ih2[1] * md.ih2[2]);
 
     // The RHS is formed on every lane: lines past the end of a ragged last
     // band read staged rows that exist (R + 3 are allocated) and their
@@ -735,7 +739,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
             for (int k = 0; k < CX; ++k)
 #pragma unroll
                 for (int q = 0; q < RL; ++q)
-                    v[q][k] = rhs_site<T, DIM>(at, q, k + HALO, ihx2, ihy2, ihz2, dt, tg, cxy, cxz, cyz);
+                    v[q][k] = rhs_site<T, DIM>(at, q, k + HALO, cdx, cdy, cdz, gxy, gxz, gyz);
         }
     }
 
@@ -1028,10 +1032,11 @@ __global__ void __launch_bounds__(kPassAThreads) passA_multi_kernel(PassAArgs a)
     const bool lane_ok = g < groups;
     const int cb_off = (rl0 + 1) * pitch + j * (CX + PADE);
 
-    const T ihx2 = (T)md.ih2[0], ihy2 = (T)md.ih2[1], ihz2 = (T)md.ih2[2];
-    const T dt = (T)md.dt, tg = (T)(2.0 * md.gamma * md.dt);
-    const T cxy = (T)(md.ih2[0] * md.ih2[1]);
-    const T cxz = (T)(md.ih2[0] * md.ih2[2]), cyz = (T)(md.ih2[1] * md.ih2[2]);
+    // folded coefficients of the RHS
+    const T cdx = (T)(md.dt * md.ih2[0]), cdy = (T)(md.dt * md.ih2[1]), cdz = (T)(md.dt * md.ih2[2]);
+    const T gxy = (T)(2.0 * md.gamma * md.dt * md.ih2[0] * md.ih2[1]);
+    const T gxz = (T)(2.0 * md.gamma * md.dt * md.ih2[0] * md.ih2[2]);
+    const T gyz = (T)(2.0 * md.gamma * md.dt * md.ih2[1] * md.ih2[2]);
 
     double pF = 0.0, pS = 0.0, pG = 0.0;
     for (int u = 0; u < nunits; ++u) {
@@ -1087,7 +1092,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_multi_kernel(PassAArgs a)
             for (int k = 0; k < CX; ++k)
 #pragma unroll
                 for (int q = 0; q < RL; ++q)
-                    v[q][k] = rhs_site<T, DIM>(at, q, k + HALO, ihx2, ihy2, ihz2, dt, tg, cxy, cxz, cyz);
+                    v[q][k] = rhs_site<T, DIM>(at, q, k + HALO, cdx, cdy, cdz, gxy, gxz, gyz);
         }
         if (active) {
             if (needF) {
@@ -1508,120 +1513,48 @@ __global__ void beta_kernel(const double* series, int64_t max_samples, int32_t m
 // --------------------------------------------------------------------------
 // ensemble statistics of beta
 // --------------------------------------------------------------------------
-constexpr int kStatThreads = 256;
+constexpr int kStatThreads = ens_stats::kThreads;
+static_assert(ens_stats::kMaxMoments == kMaxMoments, "one moment layout");
 
-// fixed-order block sum of one double per thread (result valid in thread 0)
-__device__ __forceinline__ double block_sum(double v, double* sh)
-{
-    const int tid = threadIdx.x;
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    __syncthreads();  // sh free from any earlier use
-    if ((tid & 63) == 0) sh[tid >> 6] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (tid == 0)
-        for (int w = 0; w < kStatThreads / 64; ++w) r += sh[w];
-    return r;
-}
+// beta_m(t_j) of the selected members from the recorded F slots (the same
+// formula as the beta series)
+struct SeriesBeta {
+    const double* series;
+    int64_t max_samples;
+    const int32_t* members;
+    int32_t K;
+    int64_t ncur;
+    double dt;
+    __device__ double operator()(int i, int64_t j) const
+    {
+        double G, b;
+        beta_at(series + (int64_t)members[i] * max_samples * kSeriesSlots, j, K, ncur, dt, G, b);
+        return b;
+    }
+};
 
-// One block per sample j: mu_1 = mean over the members of beta_m(t_j), then
-// mu_p = mean of (beta_m - mu_1)^p, p = 2..pmax (two passes over the members,
-// thread-strided sums in member order, then a fixed tree).  out[j][p-1].
 __global__ void __launch_bounds__(kStatThreads) moments_kernel(const double* series, int64_t max_samples,
                                                                const int32_t* members, int32_t nm,
                                                                int32_t K, int64_t ncur, double dt,
                                                                int32_t pmax, double* out, int64_t J)
 {
-    __shared__ double sh[kStatThreads / 64];
-    __shared__ double mean_sh;
-    for (int64_t jj = blockIdx.x; jj < J; jj += gridDim.x) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < nm; i += kStatThreads) {
-            double G, b;
-            beta_at(series + (int64_t)members[i] * max_samples * kSeriesSlots, jj, K, ncur, dt, G, b);
-            s += b;
-        }
-        const double tot = block_sum(s, sh);
-        if (threadIdx.x == 0) mean_sh = tot / nm;
-        __syncthreads();
-        const double mu1 = mean_sh;
-        double acc[kMaxMoments];
-#pragma unroll
-        for (int p = 0; p < kMaxMoments; ++p) acc[p] = 0.0;
-        for (int i = threadIdx.x; i < nm; i += kStatThreads) {
-            double G, b;
-            beta_at(series + (int64_t)members[i] * max_samples * kSeriesSlots, jj, K, ncur, dt, G, b);
-            const double d = b - mu1;
-            double dp = d;
-#pragma unroll
-            for (int p = 1; p < kMaxMoments; ++p) {
-                dp *= d;
-                acc[p] += dp;
-            }
-        }
-        double* o = out + jj * kMaxMoments;
-        if (threadIdx.x == 0) o[0] = mu1;
-#pragma unroll
-        for (int p = 1; p < kMaxMoments; ++p) {
-            if (p >= pmax) break;  // uniform over the block
-            const double r = block_sum(acc[p], sh);
-            if (threadIdx.x == 0) o[p] = r / nm;
-        }
-        __syncthreads();  // mean_sh is rewritten for the next sample
-    }
+    ens_stats::moments(SeriesBeta{series, max_samples, members, K, ncur, dt}, nm, J, pmax, out);
 }
 
-// Over the samples j0..j1: beta0 = time average of mu_1 (trapezoid rule on
-// the sample grid), k = least-squares slope of mu_2 = k t through the origin.
-// One block; out = {beta0, k}.
 __global__ void __launch_bounds__(kStatThreads) window_kernel(const double* mom, int64_t j0, int64_t j1,
                                                               int32_t K, double dt, double* out)
 {
-    __shared__ double sh[kStatThreads / 64];
-    const double step = (double)K * dt;
-    double a = 0.0, b = 0.0, c = 0.0;  // trapezoid sum, sum t mu2, sum t^2
-    for (int64_t j = j0 + threadIdx.x; j <= j1; j += kStatThreads) {
-        const double t = (double)(j * K) * dt;
-        b += t * mom[j * kMaxMoments + 1];
-        c += t * t;
-        if (j < j1) a += 0.5 * step * (mom[j * kMaxMoments] + mom[(j + 1) * kMaxMoments]);
-    }
-    const double A = block_sum(a, sh);
-    const double B = block_sum(b, sh);
-    const double Cc = block_sum(c, sh);
-    if (threadIdx.x == 0) {
-        out[0] = (j1 > j0) ? A / ((double)(j1 - j0) * step) : __builtin_nan("");
-        out[1] = (Cc > 0.0) ? B / Cc : __builtin_nan("");
-    }
+    ens_stats::window(mom, j0, j1, (double)K * dt, [=](int64_t j) { return (double)(j * K) * dt; }, out);
 }
 
-// Histogram of beta_m(t_j) over the members and the samples j0..j1: nbins
-// equal bins on [lo, hi), counts[0] below lo, counts[nbins + 1] at or above
-// hi, NaN not counted.  Integer atomics (order-independent).
 __global__ void __launch_bounds__(kStatThreads) hist_kernel(const double* series, int64_t max_samples,
                                                             const int32_t* members, int32_t nm, int32_t K,
                                                             int64_t ncur, double dt, int64_t j0, int64_t j1,
                                                             double lo, double hi, int32_t nbins,
                                                             unsigned long long* counts)
 {
-    const int64_t total = (j1 - j0 + 1) * (int64_t)nm;
-    const double scale = nbins / (hi - lo);
-    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
-         it += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t jj = j0 + it / nm;
-        const int i = (int)(it - (jj - j0) * nm);
-        double G, b;
-        beta_at(series + (int64_t)members[i] * max_samples * kSeriesSlots, jj, K, ncur, dt, G, b);
-        if (isnan(b)) continue;
-        int bin;
-        if (b < lo)
-            bin = 0;
-        else if (b >= hi)
-            bin = nbins + 1;
-        else
-            bin = 1 + min(nbins - 1, (int)((b - lo) * scale));
-        atomicAdd(counts + bin, 1ull);
-    }
+    ens_stats::histogram(SeriesBeta{series, max_samples, members, K, ncur, dt}, nm, j0, j1, lo, hi, nbins,
+                         counts);
 }
 
 // --------------------------------------------------------------------------

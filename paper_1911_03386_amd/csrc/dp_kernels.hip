@@ -26,6 +26,7 @@
 // Samples: F = (1/2) sum H R^2 (eq. (Fdef)), dF/dt = -sum H (1/R)(1 - ubar R)^2
 // (eq. (dFdt)), beta = -t (dF/dt)/F (eq. (betaN)).
 #include "dp_internal.h"
+#include "ensemble_stats.h"
 
 #include <hip/hip_runtime.h>
 
@@ -399,84 +400,31 @@ __global__ void __launch_bounds__(T) step_kernel(Args a, int64_t attempts)
 // ensemble statistics of the recorded beta (the same definitions as for the
 // Cahn-Hilliard ensembles: eq. (mup), eq. (beta0_stats), mu_2 = k t)
 // --------------------------------------------------------------------------
-constexpr int kStatThreads = 256;
+constexpr int kStatThreads = ens_stats::kThreads;
+static_assert(ens_stats::kMaxMoments == kMaxMoments, "one moment layout");
 
-__device__ __forceinline__ double block_sum(double v, double* sh)
-{
-    const int tid = threadIdx.x;
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    __syncthreads();
-    if ((tid & 63) == 0) sh[tid >> 6] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (tid == 0)
-        for (int w = 0; w < kStatThreads / 64; ++w) r += sh[w];
-    return r;
-}
+// beta of selected member i at sample j from the recorded series
+struct SeriesBeta {
+    const double* series;
+    int64_t J;
+    const int32_t* members;
+    __device__ double operator()(int i, int64_t j) const
+    {
+        return series[((int64_t)members[i] * J + j) * kSlots + 3];
+    }
+};
 
-__device__ __forceinline__ double beta_of(const double* series, int64_t J, int32_t m, int64_t j)
-{
-    return series[((int64_t)m * J + j) * kSlots + 3];
-}
-
-// one block per sample j: mu_1 and the central moments mu_2..mu_pmax
 __global__ void __launch_bounds__(kStatThreads) moments_kernel(const double* series, int64_t J,
                                                                const int32_t* members, int32_t nm,
                                                                int64_t count, int32_t pmax, double* out)
 {
-    __shared__ double sh[kStatThreads / 64];
-    __shared__ double mean_sh;
-    for (int64_t j = blockIdx.x; j < count; j += gridDim.x) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < nm; i += kStatThreads) s += beta_of(series, J, members[i], j);
-        const double tot = block_sum(s, sh);
-        if (threadIdx.x == 0) mean_sh = tot / nm;
-        __syncthreads();
-        const double mu1 = mean_sh;
-        double acc[kMaxMoments];
-#pragma unroll
-        for (int p = 0; p < kMaxMoments; ++p) acc[p] = 0.0;
-        for (int i = threadIdx.x; i < nm; i += kStatThreads) {
-            const double d = beta_of(series, J, members[i], j) - mu1;
-            double dp = d;
-#pragma unroll
-            for (int p = 1; p < kMaxMoments; ++p) {
-                dp *= d;
-                acc[p] += dp;
-            }
-        }
-        double* o = out + j * kMaxMoments;
-        if (threadIdx.x == 0) o[0] = mu1;
-#pragma unroll
-        for (int p = 1; p < kMaxMoments; ++p) {
-            if (p >= pmax) break;
-            const double r = block_sum(acc[p], sh);
-            if (threadIdx.x == 0) o[p] = r / nm;
-        }
-        __syncthreads();
-    }
+    ens_stats::moments(SeriesBeta{series, J, members}, nm, count, pmax, out);
 }
 
-// beta0 = trapezoid time average of mu_1 over samples j0..j1, k = least-squares
-// slope of mu_2 = k t through the origin; out = {beta0, k}
 __global__ void __launch_bounds__(kStatThreads) window_kernel(const double* mom, int64_t j0, int64_t j1,
                                                               double dts, double* out)
 {
-    __shared__ double sh[kStatThreads / 64];
-    double a = 0.0, b = 0.0, c = 0.0;
-    for (int64_t j = j0 + threadIdx.x; j <= j1; j += kStatThreads) {
-        const double t = (double)j * dts;
-        b += t * mom[j * kMaxMoments + 1];
-        c += t * t;
-        if (j < j1) a += 0.5 * dts * (mom[j * kMaxMoments] + mom[(j + 1) * kMaxMoments]);
-    }
-    const double A = block_sum(a, sh);
-    const double B = block_sum(b, sh);
-    const double Cc = block_sum(c, sh);
-    if (threadIdx.x == 0) {
-        out[0] = (j1 > j0) ? A / ((double)(j1 - j0) * dts) : __builtin_nan("");
-        out[1] = (Cc > 0.0) ? B / Cc : __builtin_nan("");
-    }
+    ens_stats::window(mom, j0, j1, dts, [=](int64_t j) { return (double)j * dts; }, out);
 }
 
 __global__ void __launch_bounds__(kStatThreads) hist_kernel(const double* series, int64_t J,
@@ -484,23 +432,7 @@ __global__ void __launch_bounds__(kStatThreads) hist_kernel(const double* series
                                                             int64_t j1, double lo, double hi, int32_t nbins,
                                                             unsigned long long* counts)
 {
-    const int64_t total = (j1 - j0 + 1) * (int64_t)nm;
-    const double scale = nbins / (hi - lo);
-    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
-         it += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t j = j0 + it / nm;
-        const int i = (int)(it - (j - j0) * nm);
-        const double b = beta_of(series, J, members[i], j);
-        if (isnan(b)) continue;
-        int bin;
-        if (b < lo)
-            bin = 0;
-        else if (b >= hi)
-            bin = nbins + 1;
-        else
-            bin = 1 + min(nbins - 1, (int)((b - lo) * scale));
-        atomicAdd(counts + bin, 1ull);
-    }
+    ens_stats::histogram(SeriesBeta{series, J, members}, nm, j0, j1, lo, hi, nbins, counts);
 }
 
 __global__ void zero_kernel(unsigned long long* p, int64_t n)
