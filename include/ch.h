@@ -95,9 +95,13 @@ typedef enum CH_ENUM_INT {
 /* One ensemble member.
  *  dim      2 or 3
  *  n[3]     points per axis (x, y, z); n[2] must be 1 when dim == 2.  Each
- *           used axis needs 8 <= n <= 4096, n a multiple of 4, and n = c * P
- *           with c in {4, 8, 16, 32, 64} and P <= 64 (every power of two from
- *           8 to 4096 qualifies); otherwise CH_EUNSUPPORTED.
+ *           used axis needs 8 <= n <= 8192 and n a multiple of 4.  x: n = c * P
+ *           with c in {4, 8, 16, 32, 64} and P <= 64 chunks (n <= 4096), or,
+ *           in 2D, P = 128 or 256 chunks of c in {4, 8, 16, 32} (lines held
+ *           by 2 or 4 wavefronts).  y, z: n = c * P with P <= 256 chunks of a
+ *           column-sweep chunk length (4..32; FP32 also 64).  Every power of
+ *           two from 8 to 8192 qualifies in 2D, to 4096 along x in 3D;
+ *           otherwise CH_EUNSUPPORTED.
  *  L[3]     domain lengths (> 0); L[2] ignored in 2D
  *  gamma    interface parameter (> 0);  dt  time step (> 0)
  *  c0, noise  initial condition C = c0 + noise (2u - 1), u in [0,1) from the
@@ -201,8 +205,12 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path);
  * in 2D; z-planes of one y-band in 3D, with a ring of staged planes).  The
  * y-solve: cy = elements per
  * lane, by = columns per block; cz/bz the same for the z-solve (ignored in
- * 2D).  CH_EUNSUPPORTED if the shape is not valid for the class (nothing
- * changes then). */
+ * 2D).  x-lines of more than 64 chunks (nx / cx = 128 or 256; 2D) take
+ * rl = 1, waves = 4 and units = 1, or units = 0 for the split form: the RHS
+ * is formed over 8 x 256 tiles into the scratch field first and the x-lines
+ * are then solved in place there (FP64, nx a multiple of 256; the form used
+ * where a line's staged rows exceed LDS).  CH_EUNSUPPORTED if the shape is
+ * not valid for the class (nothing changes then). */
 ch_status ch_num_classes(const ch_ctx* ctx, int32_t* nclasses);
 ch_status ch_set_tiles(ch_ctx* ctx, int32_t cls, int32_t cx, int32_t rl, int32_t waves,
                        int32_t units, int32_t cy, int32_t by, int32_t cz, int32_t bz);

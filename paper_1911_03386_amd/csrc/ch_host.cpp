@@ -55,7 +55,10 @@ struct ClassPlan {
     bool cn = false; // Crank-Nicolson variant of the scheme (theta = 1/2; 2D)
     // pass A
     int cx = 0, rl = 1, waves = 4, units = 1, P = 0, rpw = 0, R = 0, bands = 0, pitch = 0;
+    int wl = 0;          // wavefronts per x-line (0: a line within one wavefront, P <= 64)
+    bool split = false;  // RHS tile pass, then the x-solve in place (wide FP64 lines; units = 0)
     int64_t bpmA = 0;  // pass-A blocks per member
+    int64_t bpmP = 0;  // diagnostics partials per member (pass-A blocks, or RHS tiles of the split form)
     int64_t nblocksA = 0;
     size_t ldsA = 0;
     ColPlan col[3];  // [1] = y, [2] = z
@@ -78,11 +81,51 @@ int64_t class_size(const ClassPlan& c) { return c.nfixed > 0 ? c.nfixed : (int64
 
 int lds_pos(int xx, int cx, int pad) { return xx + (xx / cx) * pad; }
 
+int64_t split_tiles(int nx, int ny) { return (int64_t)(nx / kTileX) * ((ny + kTileY - 1) / kTileY); }
+
+// x-lines of more than 64 chunks: a line spans P / 64 wavefronts of a
+// 4-wavefront block (2D, one line per lane, one unit per block).  units = 0
+// asks for the split form.
+bool planA_wide(ClassPlan& c, int prec, int cx, int rl, int waves, int units)
+{
+    const int P = c.nx / cx;
+    const bool split = units == 0;
+    if (c.dim != 2 || c.cn || rl != 1 || waves != kPassAThreads / 64 || (units != 1 && !split)) return false;
+    if (P % 64 || !passA_wide_has(prec, cx, P / 64, split)) return false;
+    if (split && c.nx % kTileX) return false;
+    const int wl = P / 64;
+    const int R = waves / wl;
+    const int pad = passA_pad(prec), halo = passA_halo(prec);
+    if (cx % halo) return false;
+    const int pitch = lds_pos(c.nx + 2 * halo - 1, cx, pad) + 1;
+    // staged rows: the R lines and their stencil rows, or (split) the lines only
+    const size_t lds = (size_t)(split ? R : R + 3) * pitch * elem_size(prec);
+    if (lds > kLdsLimit) return false;
+    c.cx = cx;
+    c.rl = 1;
+    c.waves = waves;
+    c.units = units;
+    c.P = P;
+    c.rpw = 0;
+    c.R = R;
+    c.wl = wl;
+    c.split = split;
+    c.bands = (c.ny + R - 1) / R;
+    c.pitch = pitch;
+    c.ldsA = lds;
+    c.bpmA = c.bands;
+    c.bpmP = split ? split_tiles(c.nx, c.ny) : c.bpmA;
+    c.nblocksA = class_size(c) * c.bpmA;
+    return true;
+}
+
 bool planA(ClassPlan& c, int prec, int cx, int rl, int waves, int units)
 {
-    if (!passA_has(c.dim, cx, rl, units, c.cn) || c.nx % cx) return false;
+    if (cx < 1 || c.nx % cx) return false;
     const int P = c.nx / cx;
-    if (P < 1 || P > 64) return false;
+    if (P > 64) return planA_wide(c, prec, cx, rl, waves, units);
+    if (!passA_has(c.dim, cx, rl, units, c.cn)) return false;
+    if (P < 1) return false;
     if (waves < 1 || waves > kPassAThreads / 64) return false;
     const int rpw = (64 / P) * rl;
     const int R = waves * rpw;
@@ -108,6 +151,8 @@ bool planA(ClassPlan& c, int prec, int cx, int rl, int waves, int units)
     c.P = P;
     c.rpw = rpw;
     c.R = R;
+    c.wl = 0;
+    c.split = false;
     c.bands = (c.ny + R - 1) / R;
     c.pitch = pitch;
     c.ldsA = lds;
@@ -115,6 +160,7 @@ bool planA(ClassPlan& c, int prec, int cx, int rl, int waves, int units)
         c.bpmA = (c.bands + units - 1) / units;
     else
         c.bpmA = (int64_t)c.bands * ((c.nz + units - 1) / units);
+    c.bpmP = c.bpmA;
     c.nblocksA = class_size(c) * c.bpmA;
     return true;
 }
@@ -128,6 +174,7 @@ bool planCol(ClassPlan& c, int prec, int axis, int cy, int b)
     // a block's b columns must be contiguous in memory: y-lines (and 2D) run
     // along x only, z-lines along the whole x-y plane
     const int64_t run = axis == 1 ? c.nx : (int64_t)c.nx * c.ny;
+    if (P > (1 << kMaxScanLevels)) return false;  // the chunk scan has kMaxScanLevels levels
     if (b < 1 || (b & (b - 1)) || run % b || b * P > kColMaxThreads) return false;
     p.cy = cy;
     p.b = b;
@@ -155,6 +202,11 @@ bool default_A(ClassPlan& c, int prec)
         for (auto& p : prefs)
             if (planA(c, prec, p[0], p[1], waves, units) || planA(c, prec, p[0], p[1], waves, 1))
                 return true;
+    // lines longer than 64 chunks of 64 (2D): the widest chunks that fit,
+    // staged whole or (FP64) in the split form
+    for (int cx : {32, 16, 8, 4})
+        if (planA(c, prec, cx, 1, kPassAThreads / 64, 1) || planA(c, prec, cx, 1, kPassAThreads / 64, 0))
+            return true;
     return false;
 }
 
@@ -174,6 +226,7 @@ bool default_col(ClassPlan& c, int prec, int axis)
     for (int cy : prefs) {
         if (!col_has(prec, cy) || n % cy) continue;
         const int P = n / cy;
+        if (P > (1 << kMaxScanLevels)) continue;
         const int b = best_b(axis == 1 ? (int64_t)c.nx : (int64_t)c.nx * c.ny, P);
         if (b * P > kColMaxThreads) continue;
         const int score = std::min(b * elem_size(prec), 256);
@@ -186,11 +239,24 @@ bool default_col(ClassPlan& c, int prec, int axis)
     return bestcy && planCol(c, prec, axis, bestcy, bestb);
 }
 
-bool axis_ok(int n)
+// Grid sizes with a line-solve shape: x-lines of n = c P with P <= 64 chunks
+// in one wavefront, or (2D) P = 128 or 256 over several; y- and z-lines of up
+// to 256 chunks of a column-sweep chunk length.
+bool axis_ok(int n, int axis, int dim, int prec)
 {
-    if (n < 8 || n > 4096 || n % 4) return false;
+    if (n < 8 || n > 8192 || n % 4) return false;
+    if (axis == 0) {
+        for (int c : {4, 8, 16, 32, 64})
+            if (n % c == 0 && n / c <= 64 && n <= 4096) return true;
+        if (dim == 2)
+            for (int c : {4, 8, 16, 32, 64})
+                for (int wl : {2, 4})
+                    if (n == 64 * wl * c && (passA_wide_has(prec, c, wl, false) || passA_wide_has(prec, c, wl, true)))
+                        return true;
+        return false;
+    }
     for (int c : {4, 8, 16, 32, 64})
-        if (n % c == 0 && n / c <= 64) return true;
+        if (col_has(prec, c) && n % c == 0 && n / c <= (1 << kMaxScanLevels)) return true;
     return false;
 }
 
@@ -215,7 +281,7 @@ ch_status validate(const ch_member_desc* members, int32_t m, int prec, int32_t c
     }
     for (int i = 0; i < m; ++i) {
         const ch_member_desc& d = members[i];
-        char buf[160];
+        char buf[320];
         if (d.dim != 2 && d.dim != 3) {
             snprintf(buf, sizeof buf, "member %d: dim must be 2 or 3", i);
             err = buf;
@@ -240,10 +306,11 @@ ch_status validate(const ch_member_desc* members, int32_t m, int prec, int32_t c
             return CH_EINVAL;
         }
         for (int a = 0; a < d.dim; ++a) {
-            if (!axis_ok(d.n[a])) {
+            if (!axis_ok(d.n[a], a, d.dim, prec)) {
                 snprintf(buf, sizeof buf,
-                         "member %d: n[%d] = %d unsupported (need 8..4096, a multiple of 4, n = c*P "
-                         "with c in {4,8,16,32,64}, P <= 64)",
+                         "member %d: n[%d] = %d unsupported (need 8..8192, a multiple of 4; x: n = c*P with "
+                         "c in {4,..,64}, P <= 64 (n <= 4096), or in 2D P = 128 or 256 chunks of 4..32; "
+                         "y, z: n = c*P, P <= 256)",
                          i, a, d.n[a]);
                 err = buf;
                 return CH_EUNSUPPORTED;
@@ -386,7 +453,8 @@ void layout(const ch_member_desc* members, int32_t m, int prec, int64_t max_samp
     o = align_up(o + (size_t)e * elem_size(prec));
     for (auto& c : classes) {
         // enough partial slots for the smallest tile (one x-line per block)
-        c.partial_cap = (int64_t)c.members.size() * c.nz * c.ny;
+        // and for the RHS tiles of the split form
+        c.partial_cap = (int64_t)c.members.size() * std::max<int64_t>((int64_t)c.nz * c.ny, split_tiles(c.nx, c.ny));
         c.off_partials = o;
         o = align_up(o + sizeof(double) * 3 * (size_t)c.partial_cap);
     }
@@ -564,7 +632,7 @@ FinArgs fin_args(ch_ctx* ctx, int ci, int mode)
     f.mids = reinterpret_cast<const int32_t*>(ctx->ws + c.off_mids);
     f.nmem = (int32_t)c.members.size();
     f.K = ctx->K;
-    f.blocks_per_member = c.bpmA;
+    f.blocks_per_member = c.bpmP;
     f.partials = reinterpret_cast<const double*>(ctx->ws + c.off_partials);
     f.nstamp = ctx->d_nstamp() + ci;
     f.G = (int32_t)std::min<int64_t>(c.members.size(), 1024);
@@ -766,9 +834,10 @@ std::string plan_text(const ch_ctx* ctx)
     char buf[320];
     for (const auto& c : ctx->classes) {
         snprintf(buf, sizeof buf,
-                 "%dD %dx%dx%d %s%s x%zu: A cx=%d rl=%d P=%d waves=%d units=%d R=%d blocks=%lld lds=%zu",
+                 "%dD %dx%dx%d %s%s x%zu: A cx=%d rl=%d P=%d waves=%d units=%d R=%d blocks=%lld lds=%zu%s",
                  c.dim, c.nx, c.ny, c.nz, ctx->prec ? "f32" : "f64", c.cn ? " cn" : "", c.members.size(), c.cx, c.rl, c.P,
-                 c.waves, c.units, c.R, (long long)c.nblocksA, c.ldsA);
+                 c.waves, c.units, c.R, (long long)c.nblocksA, c.ldsA,
+                 c.split ? " split" : (c.wl ? " wide" : ""));
         s += buf;
         for (int a = 1; a < c.dim; ++a) {
             snprintf(buf, sizeof buf, " | %c cy=%d P=%d b=%d blocks=%lld", a == 1 ? 'y' : 'z',
@@ -888,7 +957,7 @@ StaticLayout static_layout(const ClassPlan& c, int prec, int32_t m, int64_t site
     S.W = o;
     o = align_up(o + (size_t)elem_size(prec) * (size_t)sites * m);
     S.partials = o;
-    o = align_up(o + sizeof(double) * 3 * (size_t)c.nblocksA);
+    o = align_up(o + sizeof(double) * 3 * (size_t)(class_size(c) * c.bpmP));
     S.steps = o;
     o = align_up(o + sizeof(int64_t));
     S.nstamp = o;
@@ -1383,10 +1452,10 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path)
         float best = 1e30f;
         int bcx = c.cx, brl = c.rl, bw = c.waves, bu = c.units;
         Shortlist& sl = shortlist[key];
-        const int unit_opts_2d[] = {1, 2, 4};
+        const int unit_opts_2d[] = {1, 2, 4, 0};  // 0: split form (lines beyond 64 chunks)
         const int unit_opts_3d[] = {1, 4, 8, 16, 32};
         const int* uo = c.dim == 3 ? unit_opts_3d : unit_opts_2d;
-        const int nuo = c.dim == 3 ? 5 : 3;
+        const int nuo = c.dim == 3 ? 5 : 4;
         for (int waves : {4, 2, 1})
             for (int rl : {1, 2, 4})
                 for (int cx : {4, 8, 16, 32, 64})
@@ -1772,7 +1841,7 @@ ch_status ch_step_static(const ch_member_desc* members, int32_t m, ch_precision 
     f.mids = a.mids;
     f.nmem = m;
     f.K = kNoCadence;
-    f.blocks_per_member = c.bpmA;
+    f.blocks_per_member = c.bpmP;
     f.partials = a.partials;
     f.nstamp = nstamp;
     f.max_samples = 1;

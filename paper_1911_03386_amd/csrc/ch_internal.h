@@ -7,13 +7,15 @@
 
 namespace chk {
 
-constexpr int kMaxScanLevels = 7;  // (A^c)^(2^s), s < 7: enough for P <= 128 chunks
+constexpr int kMaxScanLevels = 8;  // (A^c)^(2^s), s < 8: enough for P <= 256 chunks
 constexpr int kWaveScanLevels = 6; // lanes of one line inside a wavefront: P <= 64
 constexpr int kSeriesSlots = 5;    // F(jK-1), F(jK), F(jK+1), <C>(jK), G_id(jK)
 constexpr int kPassAThreads = 256; // 4 wavefronts
 constexpr int kColMaxThreads = 512;
 constexpr int kMaxMoments = 8;     // ensemble statistics: mu_1 .. mu_8
 constexpr int kPrefetchVecs = 12;  // several-unit pass A: 16-byte vectors per lane prefetched for the next unit
+constexpr int kTileY = 8;          // RHS pass of the split form: tile rows (4 wavefronts x 2 rows of 32 lanes)
+constexpr int kTileX = 256;        //   ... and tile columns (8 per lane)
 
 // Coefficients of the periodic solve (I + rho [1,-4,6,-4,1]) y = x along one
 // axis of one member, factored as y = ikappa * Qa^{-1} Qc^{-1} x with the
@@ -77,8 +79,8 @@ struct PassAArgs {
     const int32_t* mids;       // member ids of this class
     int32_t nmem;              // members in this class
     int32_t nx, ny, nz;
-    int32_t P;                 // lanes per x-line (chunks)
-    int32_t rows_per_wave;     // x-lines per wavefront (line groups x lines per lane)
+    int32_t P;                 // chunks per x-line (lanes; above 64 a line spans P / 64 wavefronts)
+    int32_t rows_per_wave;     // x-lines per wavefront (line groups x lines per lane; 0 above 64 chunks)
     int32_t waves;             // wavefronts per block (1, 2 or 4)
     int32_t R;                 // x-lines per block (= waves * rows_per_wave)
     int32_t bands_y;           // y-bands per (member, z) = ceil(ny / R)
@@ -139,6 +141,8 @@ hipError_t launch_hist(const double* series, int64_t max_samples, const int32_t*
                        int32_t nbins, unsigned long long* counts, hipStream_t s);
 
 bool passA_has(int dim, int cx, int rl, int units, bool cn = false);  // units > 1: several units per block
+// lines of 64 wl chunks of cx (2D): split = RHS pass (kTileY x kTileX tiles) then the x-solve in place
+bool passA_wide_has(int prec, int cx, int wl, bool split);
 bool col_has(int prec, int cy);
 int passA_pad(int prec);       // LDS padding (elements) after every chunk
 int passA_halo(int prec);      // periodic halo columns on each side of an LDS row

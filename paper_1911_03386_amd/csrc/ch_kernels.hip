@@ -457,6 +457,161 @@ struct PadOf<float> {
 // --------------------------------------------------------------------------
 // pass A: RHS + diagnostics + x-line solves
 // --------------------------------------------------------------------------
+// Stages rows y0 - ylo + r (r < nrows, periodic in y) of the planes
+// z - 1 + pl (pl < npl; 3D, periodic in z) of a member's field into LDS row
+// pl * planeStride + r * pitch: element x at HALO + x in the chunk layout, and
+// (halos) one vector of periodic halo on either side of every row.
+// Interior: a wavefront stages whole rows (rows of all planes go to the
+// wavefronts round-robin), its lanes take consecutive 16-byte vectors of a
+// row in segments of 64, and each lane issues NB loads before it writes any
+// of them to LDS.  Row bases are wave-uniform (scalar registers).  Halos: one
+// vector on each side of every row, one per thread.
+template <typename T, int DIM, int CX>
+__device__ __forceinline__ void stage_rows(T* sC, __amdgpu_buffer_rsrc_t rC, int nrows, int npl, int ylo,
+                                           int y0, int z, int nx, int ny, int nz, int pitch, int planeStride,
+                                           bool halos)
+{
+    constexpr int PADE = PadOf<T>::v;
+    constexpr int VEC = Vec16<T>::n;
+    constexpr int HALO = VEC;
+    using VT = typename Vec16<T>::type;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int nthreads = blockDim.x;  // 64 * waves
+    const int nwaves = nthreads >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nvec = nx / VEC;
+    const int nrows_all = npl * nrows;
+    const int nseg = (nvec + 63) >> 6;
+    {
+        constexpr int NB = 8;
+        int pl = 0, r = wv, seg = 0;  // wave-uniform cursor (plane, row, segment)
+        while (r >= nrows) {
+            r -= nrows;
+            ++pl;
+        }
+        while (pl < npl) {
+            VT val[NB];
+            int dst[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                dst[i] = -1;
+                if (pl < npl) {
+                    const int zz = (DIM == 3) ? wrapi(z - 1 + pl, nz) : 0;
+                    const int yy = wrapi(y0 - ylo + r, ny);
+                    const int rowo = (zz * ny + yy) * nx;  // wave-uniform
+                    const int xi = seg * 64 + lane;
+                    if (xi < nvec) {
+                        const uint32_t xs = (uint32_t)xi * VEC, xx = xs + HALO;
+                        val[i] = buf_load16<VT>(rC, (int)xs * (int)sizeof(T), rowo * (int)sizeof(T));
+                        dst[i] = pl * planeStride + r * pitch + (int)(xx + xx / CX * PADE);
+                    }
+                    if (++seg == nseg) {
+                        seg = 0;
+                        r += nwaves;
+                        while (r >= nrows) {
+                            r -= nrows;
+                            ++pl;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+                if (dst[i] >= 0) {
+                    T e[VEC];
+                    vec_get<T>(val[i], e);
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) sC[dst[i] + q] = e[q];
+                }
+        }
+        if (halos)
+            for (int h = tid; h < 2 * nrows_all; h += nthreads) {
+                const int rid = h >> 1, pl = rid / nrows, r = rid - pl * nrows;
+                const int zz = (DIM == 3) ? wrapi(z - 1 + pl, nz) : 0;
+                const int yy = wrapi(y0 - ylo + r, ny);
+                // left halo: the last vector of the row; right halo: the first
+                const int xs = (h & 1) ? 0 : nx - HALO;
+                const int xx = (h & 1) ? nx + HALO : 0;
+                const VT val = buf_load16<VT>(rC, ((zz * ny + yy) * nx + xs) * (int)sizeof(T), 0);
+                T e[VEC];
+                vec_get<T>(val, e);
+                const int d = pl * planeStride + r * pitch + xx + (xx / CX) * PADE;
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) sC[d + q] = e[q];
+            }
+    }
+}
+
+// Per-lane partial sums of the diagnostics over the lane's chunk of its RL
+// lines (FP64): F (bulk + gradient energy, forward differences), sum C, and
+// sum |grad_h mu|^2 with mu = C^3 - C - gamma lap_h C.  cb points at the
+// lane's chunk in the staged rows (line rl0, chunk start); rows and planes of
+// the stencil are at +-pitch and +-planeStride.
+template <typename T, int DIM, int CX, int RL>
+__device__ __forceinline__ void diag_sums(const T* cb, int pitch, int planeStride, unsigned rowmask,
+                                          const MemberDev& md, int conv, bool needF, bool needG, double& pF,
+                                          double& pS, double& pG)
+{
+    constexpr int PADE = PadOf<T>::v;
+    constexpr int HALO = Vec16<T>::n;
+#define AT(dz, dy, m) cb[(dz) * planeStride + (dy) * pitch + (m) + ((m) / CX) * PADE]
+    if (needF) {
+        const double cbulk = conv ? 0.5 : 0.25;
+        const double hg = 0.5 * md.gamma;
+        const double dx2 = md.ih2[0], dy2 = md.ih2[1], dz2 = md.ih2[2];
+#pragma unroll
+        for (int q = 0; q < RL; ++q) {
+            if (!((rowmask >> q) & 1)) continue;
+#pragma unroll
+            for (int k = 0; k < CX; ++k) {
+                const int m0 = k + HALO;
+                const double c = (double)AT(0, q, m0);
+                const double ex = (double)AT(0, q, m0 + 1) - c;
+                const double ey = (double)AT(0, q + 1, m0) - c;
+                double gr = ex * ex * dx2 + ey * ey * dy2;
+                if (DIM == 3) {
+                    const double ez = (double)AT(1, q, m0) - c;
+                    gr += ez * ez * dz2;
+                }
+                const double qq = c * c - 1.0;
+                pF += cbulk * qq * qq + hg * gr;
+                pS += c;
+            }
+        }
+    }
+    if (needG) {
+        const double gam = md.gamma;
+        const double dx2 = md.ih2[0], dy2 = md.ih2[1], dz2 = md.ih2[2];
+        // chemical potential mu = C^3 - C - gamma lap_h C at (dz, dy, m)
+        auto MU = [&](int dz, int dy, int m) -> double {
+            const double u = (double)AT(dz, dy, m);
+            double l = ((double)AT(dz, dy, m + 1) - 2.0 * u + (double)AT(dz, dy, m - 1)) * dx2 +
+                       ((double)AT(dz, dy + 1, m) - 2.0 * u + (double)AT(dz, dy - 1, m)) * dy2;
+            if (DIM == 3)
+                l += ((double)AT(dz + 1, dy, m) - 2.0 * u + (double)AT(dz - 1, dy, m)) * dz2;
+            return u * u * u - u - gam * l;
+        };
+#pragma unroll
+        for (int q = 0; q < RL; ++q) {
+            if (!((rowmask >> q) & 1)) continue;
+#pragma unroll
+            for (int k = 0; k < CX; ++k) {
+                const int m0 = k + HALO;
+                const double mu = MU(0, q, m0);
+                const double gx = MU(0, q, m0 + 1) - mu;
+                const double gy = MU(0, q + 1, m0) - mu;
+                double qq = gx * gx * dx2 + gy * gy * dy2;
+                if (DIM == 3) {
+                    const double gz = MU(1, q, m0) - mu;
+                    qq += gz * gz * dz2;
+                }
+                pG += qq;
+            }
+        }
+    }
+#undef AT
+}
+
 // A lane's results (lines rl0 .. rl0+RL-1, chunk j) go to LDS rows of `so`
 // in the staging layout, and each wavefront then stores the lines it holds
 // itself (lines wv*rpw .. wv*rpw+rpw-1 of the unit) with coalesced 16-byte
@@ -583,7 +738,6 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     constexpr int VEC = Vec16<T>::n;
     constexpr int HALO = VEC;
     static_assert(CX % VEC == 0, "LDS layout assumes vector-aligned chunks");
-    using VT = typename Vec16<T>::type;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
 
@@ -612,7 +766,6 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     const bool solve = (a.mode != MODE_DIAG);
 
     // ---- stage C rows (with periodic halos) in LDS --------------------------
-    const int nthreads = blockDim.x;  // 64 * waves
     // staged rows: y0 - YLO .. y0 + Ract - 1 + (rows below); the
     // Crank-Nicolson variant reads two rows on either side (D_y^2)
     constexpr int YLO = CN ? 2 : 1;
@@ -623,72 +776,9 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     const int nrows = Ract + (CN ? 4 : (needG ? 3 : 2));
     const int npl = (DIM == 3) ? (needG ? 4 : 3) : 1;
     const int nvec = nx / VEC;
-    // Interior: a wavefront stages whole rows (rows of all planes go to the
-    // wavefronts round-robin), its lanes take consecutive 16-byte vectors of a
-    // row in segments of 64, and each lane issues NB loads before it writes
-    // any of them to LDS.  Row bases are wave-uniform (scalar registers).
-    // Halos: one vector on each side of every row, one per thread.
-    const int nwaves = nthreads >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
-    const int nrows_all = npl * nrows;
-    const int nseg = (nvec + 63) >> 6;
-    {
-        constexpr int NB = 8;
-        int pl = 0, r = wv, seg = 0;  // wave-uniform cursor (plane, row, segment)
-        while (r >= nrows) {
-            r -= nrows;
-            ++pl;
-        }
-        while (pl < npl) {
-            VT val[NB];
-            int dst[NB];
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                dst[i] = -1;
-                if (pl < npl) {
-                    const int zz = (DIM == 3) ? wrapi(z - 1 + pl, nz) : 0;
-                    const int yy = wrapi(y0 - YLO + r, ny);
-                    const int rowo = (zz * ny + yy) * nx;  // wave-uniform
-                    const int xi = seg * 64 + lane;
-                    if (xi < nvec) {
-                        const uint32_t xs = (uint32_t)xi * VEC, xx = xs + HALO;
-                        val[i] = buf_load16<VT>(rC, (int)xs * (int)sizeof(T), rowo * (int)sizeof(T));
-                        dst[i] = pl * planeStride + r * pitch + (int)(xx + xx / CX * PADE);
-                    }
-                    if (++seg == nseg) {
-                        seg = 0;
-                        r += nwaves;
-                        while (r >= nrows) {
-                            r -= nrows;
-                            ++pl;
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < NB; ++i)
-                if (dst[i] >= 0) {
-                    T e[VEC];
-                    vec_get<T>(val[i], e);
-#pragma unroll
-                    for (int q = 0; q < VEC; ++q) sC[dst[i] + q] = e[q];
-                }
-        }
-        for (int h = tid; h < 2 * nrows_all; h += nthreads) {
-            const int rid = h >> 1, pl = rid / nrows, r = rid - pl * nrows;
-            const int zz = (DIM == 3) ? wrapi(z - 1 + pl, nz) : 0;
-            const int yy = wrapi(y0 - YLO + r, ny);
-            // left halo: the last vector of the row; right halo: the first
-            const int xs = (h & 1) ? 0 : nx - HALO;
-            const int xx = (h & 1) ? nx + HALO : 0;
-            const VT val = buf_load16<VT>(rC, ((zz * ny + yy) * nx + xs) * (int)sizeof(T), 0);
-            T e[VEC];
-            vec_get<T>(val, e);
-            const int d = pl * planeStride + r * pitch + xx + (xx / CX) * PADE;
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) sC[d + q] = e[q];
-        }
-    }
+    const int nthreads = blockDim.x;  // 64 * waves
+    stage_rows<T, DIM, CX>(sC, rC, nrows, npl, YLO, y0, z, nx, ny, nz, pitch, planeStride, true);
     __syncthreads();
 
     // ---- per-lane work: one chunk of CX elements of RL adjacent x-lines ------
@@ -745,60 +835,10 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
 
     double pF = 0.0, pS = 0.0, pG = 0.0;
     if (active) {
-        if (needF) {
-            const double cbulk = a.conv ? 0.5 : 0.25;
-            const double hg = 0.5 * md.gamma;
-            const double dx2 = md.ih2[0], dy2 = md.ih2[1], dz2 = md.ih2[2];
+        unsigned rm = 0;
 #pragma unroll
-            for (int q = 0; q < RL; ++q) {
-                if (!rowok[q]) continue;
-#pragma unroll
-                for (int k = 0; k < CX; ++k) {
-                    const int m0 = k + HALO;
-                    const double c = (double)AT(0, q, m0);
-                    const double ex = (double)AT(0, q, m0 + 1) - c;
-                    const double ey = (double)AT(0, q + 1, m0) - c;
-                    double gr = ex * ex * dx2 + ey * ey * dy2;
-                    if (DIM == 3) {
-                        const double ez = (double)AT(1, q, m0) - c;
-                        gr += ez * ez * dz2;
-                    }
-                    const double qq = c * c - 1.0;
-                    pF += cbulk * qq * qq + hg * gr;
-                    pS += c;
-                }
-            }
-        }
-        if (needG) {
-            const double gam = md.gamma;
-            const double dx2 = md.ih2[0], dy2 = md.ih2[1], dz2 = md.ih2[2];
-            // chemical potential mu = C^3 - C - gamma lap_h C at (dz, dy, m)
-            auto MU = [&](int dz, int dy, int m) -> double {
-                const double u = (double)AT(dz, dy, m);
-                double l = ((double)AT(dz, dy, m + 1) - 2.0 * u + (double)AT(dz, dy, m - 1)) * dx2 +
-                           ((double)AT(dz, dy + 1, m) - 2.0 * u + (double)AT(dz, dy - 1, m)) * dy2;
-                if (DIM == 3)
-                    l += ((double)AT(dz + 1, dy, m) - 2.0 * u + (double)AT(dz - 1, dy, m)) * dz2;
-                return u * u * u - u - gam * l;
-            };
-#pragma unroll
-            for (int q = 0; q < RL; ++q) {
-                if (!rowok[q]) continue;
-#pragma unroll
-                for (int k = 0; k < CX; ++k) {
-                    const int m0 = k + HALO;
-                    const double mu = MU(0, q, m0);
-                    const double gx = MU(0, q, m0 + 1) - mu;
-                    const double gy = MU(0, q + 1, m0) - mu;
-                    double qq = gx * gx * dx2 + gy * gy * dy2;
-                    if (DIM == 3) {
-                        const double gz = MU(1, q, m0) - mu;
-                        qq += gz * gz * dz2;
-                    }
-                    pG += qq;
-                }
-            }
-        }
+        for (int q = 0; q < RL; ++q) rm |= rowok[q] ? (1u << q) : 0u;
+        diag_sums<T, DIM, CX, RL>(cb, pitch, planeStride, rm, md, a.conv, needF, needG, pF, pS, pG);
     }
 #undef AT
 
@@ -879,6 +919,350 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     if (needF && tid == 0) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         for (int w = 0; w < nthreads / 64; ++w) {
+            s0 += red[w][0];
+            s1 += red[w][1];
+            s2 += red[w][2];
+        }
+        a.partials[blk * 3 + 0] = s0;
+        a.partials[blk * 3 + 1] = s1;
+        a.partials[blk * 3 + 2] = s2;
+    }
+}
+
+// --------------------------------------------------------------------------
+// pass A for lines longer than one wavefront (2D)
+// --------------------------------------------------------------------------
+// A line of P = 64 WL chunks is held by WL wavefronts (lane = chunk within
+// the wavefront's segment of 64 chunks); a block of 4 wavefronts holds
+// R = 4 / WL lines.  The chunk scans run inside each wavefront as in pass A
+// and are then combined over the line's wavefronts through LDS.  With T_w the
+// end state of segment w from a zero start and A64 = (A^c)^64 the transfer
+// over one segment, the zero-start state entering segment w is
+// S_w = A64 S_{w-1} + T_{w-1} (S_0 = 0), the ring closes with
+// r = (I - A^n)^{-1} S_WL, and chunk j = 64 w + lane enters with
+// (A^c)^lane (A64^w r + S_w) plus the exclusive prefix inside the segment.
+// The anti-causal recursion mirrors this from the right end.
+// XONLY: the RHS is already in W (rhs_tile_kernel formed it and took the
+// diagnostics); only the block's lines are staged, then solved in place.
+template <typename T, int CX, int WL, bool XONLY>
+__global__ void __launch_bounds__(kPassAThreads) passA_wide_kernel(PassAArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* sC = reinterpret_cast<T*>(lds_raw);
+    __shared__ double red[kPassAThreads / 64][3];
+    __shared__ T sst[kPassAThreads / 64][2];  // per wavefront: scan end state (or chunk-sum total)
+
+    constexpr int PADE = PadOf<T>::v;
+    constexpr int VEC = Vec16<T>::n;
+    constexpr int HALO = VEC;
+    constexpr int R = (kPassAThreads / 64) / WL;  // lines per block
+    static_assert(CX % VEC == 0 && R >= 1 && (kPassAThreads / 64) % WL == 0, "wide pass A shape");
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int li = wv / WL, wl = wv - li * WL;  // line of the block, wavefront within the line
+    const int nx = a.nx, ny = a.ny;
+
+    const int64_t blk = xcd_remap(blockIdx.x, a.nblocks);
+    const int mloc = (int)(blk / a.bands_y);
+    const int y0 = (int)(blk - (int64_t)mloc * a.bands_y) * R;
+    const MemberDev& md = a.mem[a.mids[mloc]];
+    const uint32_t bytes = (uint32_t)(md.sites * (int64_t)sizeof(T));
+    T* Wout = reinterpret_cast<T*>(a.W) + md.off;
+    const T* src = XONLY ? Wout : reinterpret_cast<const T*>(a.C) + md.off;
+
+    const int64_t n = *a.step;
+    const int K = a.K;
+    bool needF = false, needG = false;
+    if (!XONLY) {
+        if (a.mode == MODE_STEP) {
+            needG = (n % K) == 0;
+            needF = needG || (n >= 1 && ((n - 1) % K) == 0) || (((n + 1) % K) == 0);
+        } else if (a.mode == MODE_DIAG) {
+            needF = needG = true;
+        }
+    }
+    const bool solve = (a.mode != MODE_DIAG);
+
+    constexpr int YLO = XONLY ? 0 : 1;
+    const int pitch = a.pitch;
+    const int Ract = min(R, ny - y0);
+    const int nrows = XONLY ? Ract : Ract + (needG ? 3 : 2);
+    stage_rows<T, 2, CX>(sC, buffer_of(src, bytes), nrows, 1, YLO, y0, 0, nx, ny, 1, pitch, 0, !XONLY);
+    __syncthreads();
+
+    // lines past the end of a ragged last band compute on rows that exist
+    // (R + 3 are allocated; R in the XONLY form) and are never stored or summed
+    const int j = wl * 64 + lane;  // chunk of the line
+    const bool active = li < Ract;
+    const T* cb = sC + (li + YLO) * pitch + j * (CX + PADE);
+    T v[1][CX];
+    if (XONLY) {
+#pragma unroll
+        for (int k = 0; k < CX; ++k) {
+            const int m = k + HALO;
+            v[0][k] = cb[m + (m / CX) * PADE];
+        }
+    } else if (solve) {
+        const T cdx = (T)(md.dt * md.ih2[0]), cdy = (T)(md.dt * md.ih2[1]);
+        const T gxy = (T)(2.0 * md.gamma * md.dt * md.ih2[0] * md.ih2[1]);
+        auto at = [&](int, int dy, int m) { return cb[dy * pitch + m + (m / CX) * PADE]; };
+#pragma unroll
+        for (int k = 0; k < CX; ++k) v[0][k] = rhs_site<T, 2>(at, 0, k + HALO, cdx, cdy, T(0), gxy, T(0), T(0));
+    }
+    double pF = 0.0, pS = 0.0, pG = 0.0;
+    if (!XONLY && active) diag_sums<T, 2, CX, 1>(cb, pitch, 0, 1u, md, a.conv, needF, needG, pF, pS, pG);
+
+    // ---- x-line solves across the line's wavefronts ------------------------
+    T mean = T(0);
+    if (solve) {
+        const AxisCoef& ac = md.ax[0];
+        LineCoef<T> cf;
+        load_coef(cf, ac, 64);
+        T A64[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) A64[i] = (T)ac.Mp[kWaveScanLevels][i];
+        ScanLanes SL;
+        make_lanes(SL, lane, 0, 64);
+        // the line mean: chunk sums scanned inside the wavefront, the
+        // wavefront totals added in order (the same order for every wavefront
+        // of the line)
+        T cs = T(0);
+#pragma unroll
+        for (int k = 0; k < CX; ++k) cs += v[0][k];
+#pragma unroll
+        for (int s = 0; s < kWaveScanLevels; ++s) {
+            const T y = lane_get(SL.up[s], cs);
+            if (lane >= (1 << s)) cs += y;
+        }
+        if (lane == 63) sst[wv][0] = cs;
+        __syncthreads();
+        T tot = T(0);
+        for (int w = 0; w < WL; ++w) tot += sst[li * WL + w][0];
+        mean = tot * (T)ac.inv_n;
+#pragma unroll
+        for (int k = 0; k < CX; ++k) v[0][k] -= mean;
+        __syncthreads();  // sst is rewritten below
+
+        // causal recursion
+        T e0, e1;
+        fwd_zero(v[0], cf.a1, cf.a2, e0, e1);
+#pragma unroll
+        for (int s = 0; s < kWaveScanLevels; ++s) {
+            T y0v = lane_get(SL.up[s], e0), y1v = lane_get(SL.up[s], e1);
+            if (lane >= (1 << s)) {
+                mv(cf.Mp[s], y0v, y1v);
+                e0 += y0v;
+                e1 += y1v;
+            }
+        }
+        if (lane == 63) {
+            sst[wv][0] = e0;
+            sst[wv][1] = e1;
+        }
+        __syncthreads();
+        {
+            T S0 = T(0), S1 = T(0), U0 = T(0), U1 = T(0);
+            for (int w = 0; w < WL; ++w) {
+                if (w == wl) {
+                    U0 = S0;
+                    U1 = S1;
+                }
+                mv(A64, S0, S1);
+                S0 += sst[li * WL + w][0];
+                S1 += sst[li * WL + w][1];
+            }
+            T r0 = cf.W[0] * S0 + cf.W[1] * S1, r1 = cf.W[2] * S0 + cf.W[3] * S1;
+            for (int w = 0; w < wl; ++w) mv(A64, r0, r1);
+            r0 += U0;
+            r1 += U1;
+#pragma unroll
+            for (int s = 0; s < kWaveScanLevels; ++s)
+                if (lane & (1 << s)) mv(cf.Mp[s], r0, r1);
+            T p0 = lane_get(SL.up[0], e0), p1 = lane_get(SL.up[0], e1);
+            if (lane == 0) {
+                p0 = T(0);
+                p1 = T(0);
+            }
+            fwd_true(v[0], cf.a1, cf.a2, p0 + r0, p1 + r1, T(0));
+        }
+        __syncthreads();  // sst is rewritten below
+
+        // anti-causal recursion
+        bwd_zero(v[0], cf.a1, cf.a2, e0, e1);
+#pragma unroll
+        for (int s = 0; s < kWaveScanLevels; ++s) {
+            T y0v = lane_get(SL.dn[s], e0), y1v = lane_get(SL.dn[s], e1);
+            if (lane + (1 << s) < 64) {
+                mv(cf.Mp[s], y0v, y1v);
+                e0 += y0v;
+                e1 += y1v;
+            }
+        }
+        if (lane == 0) {
+            sst[wv][0] = e0;
+            sst[wv][1] = e1;
+        }
+        __syncthreads();
+        {
+            T S0 = T(0), S1 = T(0), U0 = T(0), U1 = T(0);
+            for (int w = WL - 1; w >= 0; --w) {
+                if (w == wl) {
+                    U0 = S0;
+                    U1 = S1;
+                }
+                mv(A64, S0, S1);
+                S0 += sst[li * WL + w][0];
+                S1 += sst[li * WL + w][1];
+            }
+            T r0 = cf.W[0] * S0 + cf.W[1] * S1, r1 = cf.W[2] * S0 + cf.W[3] * S1;
+            for (int w = WL - 1; w > wl; --w) mv(A64, r0, r1);
+            r0 += U0;
+            r1 += U1;
+#pragma unroll
+            for (int s = 0; s < kWaveScanLevels; ++s)
+                if ((63 - lane) & (1 << s)) mv(cf.Mp[s], r0, r1);
+            T p0 = lane_get(SL.dn[0], e0), p1 = lane_get(SL.dn[0], e1);
+            if (lane == 63) {
+                p0 = T(0);
+                p1 = T(0);
+            }
+            bwd_true(v[0], cf.a1, cf.a2, p0 + r0, p1 + r1, cf.ik, mean);
+        }
+    }
+
+    // ---- diagnostics partials -------------------------------------------------
+    if (needF) {
+        for (int off = 32; off > 0; off >>= 1) {
+            pF += __shfl_down(pF, off, 64);
+            pS += __shfl_down(pS, off, 64);
+            pG += __shfl_down(pG, off, 64);
+        }
+        if (lane == 0) {
+            red[wv][0] = pF;
+            red[wv][1] = pS;
+            red[wv][2] = pG;
+        }
+    }
+    __syncthreads();  // LDS stencil reads done; wavefront partials visible
+
+    // ---- each wavefront stores its own segment of its line through LDS -------
+    if (solve) {
+        const bool ok[1] = {active};
+        const int seg0 = wl * 64 * CX;  // first element of the segment
+        write_back<T, CX, 1>(sC + YLO * pitch + seg0 + (seg0 / CX) * PADE, pitch, v, ok, li, lane, li, lane, 1,
+                             Ract, 64 * CX / VEC, buffer_of(Wout, bytes), y0 * nx + seg0, nx);
+    }
+
+    if (!XONLY) {
+        if (blk == 0 && tid == 0 && a.mode != MODE_TIMING) *a.nstamp = n;
+        if (needF && tid == 0) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int w = 0; w < kPassAThreads / 64; ++w) {
+                s0 += red[w][0];
+                s1 += red[w][1];
+                s2 += red[w][2];
+            }
+            a.partials[blk * 3 + 0] = s0;
+            a.partials[blk * 3 + 1] = s1;
+            a.partials[blk * 3 + 2] = s2;
+        }
+    }
+}
+
+// RHS pass of the split form (2D): the RHS of the scheme over a tile of
+// kTileY x kTileX sites into W, and the tile's diagnostics partials; the
+// XONLY wide pass A then solves the x-lines of W in place.  It serves lines
+// whose staged rows do not fit LDS.  Threads: kTileY rows x 32 lanes, a lane
+// a chunk of kTileX / 32 sites, in the padded chunk layout of pass A (so the
+// stencil and diagnostics helpers apply unchanged).
+template <typename T>
+__global__ void __launch_bounds__(kPassAThreads) rhs_tile_kernel(PassAArgs a)
+{
+    constexpr int TY = kTileY, TX = kTileX, CT = kTileX / 32;
+    constexpr int PADE = PadOf<T>::v;
+    constexpr int VEC = Vec16<T>::n;
+    constexpr int HALO = VEC;
+    constexpr int RW = TX + 2 * HALO;  // staged row: x0 - HALO .. x0 + TX + HALO - 1
+    constexpr int PITCH = RW + ((RW - 1) / CT) * PADE + 1;
+    constexpr int NVR = RW / VEC;
+    static_assert(TY * 32 == kPassAThreads && CT % VEC == 0, "tile shape");
+    using VT = typename Vec16<T>::type;
+    __shared__ __align__(16) T sT[(TY + 3) * PITCH];
+    __shared__ double red[kPassAThreads / 64][3];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nx = a.nx, ny = a.ny;
+    const int tiles_x = nx / TX;
+    const int64_t per_member = (int64_t)tiles_x * ((ny + TY - 1) / TY);
+    const int64_t blk = xcd_remap(blockIdx.x, a.nblocks);
+    const int mloc = (int)(blk / per_member);
+    const int t = (int)(blk - (int64_t)mloc * per_member);
+    const int y0 = (t / tiles_x) * TY, x0 = (t % tiles_x) * TX;
+    const MemberDev& md = a.mem[a.mids[mloc]];
+    const uint32_t bytes = (uint32_t)(md.sites * (int64_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rC = buffer_of(reinterpret_cast<const T*>(a.C) + md.off, bytes);
+
+    const int64_t n = *a.step;
+    const int K = a.K;
+    bool needF = false, needG = false;
+    if (a.mode == MODE_STEP) {
+        needG = (n % K) == 0;
+        needF = needG || (n >= 1 && ((n - 1) % K) == 0) || (((n + 1) % K) == 0);
+    } else if (a.mode == MODE_DIAG) {
+        needF = needG = true;
+    }
+    const bool store = (a.mode != MODE_DIAG);
+
+    // stage rows y0 - 1 .. y0 + Tact (+1 for the gradient of mu), periodic
+    const int Tact = min(TY, ny - y0);
+    const int nrows = Tact + (needG ? 3 : 2);
+    for (int i = tid; i < nrows * NVR; i += kPassAThreads) {
+        const int r = i / NVR, vi = i - r * NVR;
+        const int yy = wrapi(y0 - 1 + r, ny);
+        const int xs = wrapi(x0 - HALO + vi * VEC, nx);  // a whole vector: nx and x0 are multiples of VEC
+        const VT val = buf_load16<VT>(rC, (yy * nx + xs) * (int)sizeof(T), 0);
+        T e[VEC];
+        vec_get<T>(val, e);
+        const int xx = vi * VEC;
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) sT[r * PITCH + (xx + q) + ((xx + q) / CT) * PADE] = e[q];
+    }
+    __syncthreads();
+
+    const int row = tid >> 5, jx = tid & 31;
+    const bool ok = row < Tact;
+    const T* cb = sT + (row + 1) * PITCH + jx * (CT + PADE);
+    double pF = 0.0, pS = 0.0, pG = 0.0;
+    if (ok) diag_sums<T, 2, CT, 1>(cb, PITCH, 0, 1u, md, a.conv, needF, needG, pF, pS, pG);
+    if (store && ok) {
+        const T cdx = (T)(md.dt * md.ih2[0]), cdy = (T)(md.dt * md.ih2[1]);
+        const T gxy = (T)(2.0 * md.gamma * md.dt * md.ih2[0] * md.ih2[1]);
+        auto at = [&](int, int dy, int m) { return cb[dy * PITCH + m + (m / CT) * PADE]; };
+        T v[CT];
+#pragma unroll
+        for (int k = 0; k < CT; ++k) v[k] = rhs_site<T, 2>(at, 0, k + HALO, cdx, cdy, T(0), gxy, T(0), T(0));
+        const __amdgpu_buffer_rsrc_t rW = buffer_of(reinterpret_cast<T*>(a.W) + md.off, bytes);
+        const int o = ((y0 + row) * nx + x0 + jx * CT) * (int)sizeof(T);
+#pragma unroll
+        for (int k = 0; k < CT; k += VEC) buf_store16<VT>(vec_make<T>(v + k), rW, o + k * (int)sizeof(T), 0);
+    }
+    if (needF) {
+        for (int off = 32; off > 0; off >>= 1) {
+            pF += __shfl_down(pF, off, 64);
+            pS += __shfl_down(pS, off, 64);
+            pG += __shfl_down(pG, off, 64);
+        }
+        if (lane == 0) {
+            red[wave][0] = pF;
+            red[wave][1] = pS;
+            red[wave][2] = pG;
+        }
+    }
+    __syncthreads();
+    if (blk == 0 && tid == 0 && a.mode != MODE_TIMING) *a.nstamp = n;
+    if (needF && tid == 0) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int w = 0; w < kPassAThreads / 64; ++w) {
             s0 += red[w][0];
             s1 += red[w][1];
             s2 += red[w][2];
@@ -1660,6 +2044,79 @@ bool passA_has(int dim, int cx, int rl, int units, bool cn)
     return false;
 }
 
+// (chunk length, wavefronts per line) of lines longer than one wavefront
+#define CH_WIDE_SHAPES(X) X(4, 4) X(8, 2) X(8, 4) X(16, 2) X(16, 4) X(32, 2) X(32, 4)
+// ... and of the split form (FP64 lines whose staged rows exceed LDS)
+#define CH_SPLIT_SHAPES(X) X(4, 4) X(32, 4)
+
+template <typename T, int CX, int WL, bool XONLY>
+static hipError_t launchW(const PassAArgs& a, size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    auto k = passA_wide_kernel<T, CX, WL, XONLY>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return launch_k(k, (unsigned)a.nblocks, kPassAThreads, lds, s, a, ev0, ev1);
+}
+
+bool passA_wide_has(int prec, int cx, int wl, bool split)
+{
+    if (split) {
+        if (prec != 0) return false;
+#define X(C, W) \
+    if (cx == C && wl == W) return true;
+        CH_SPLIT_SHAPES(X)
+#undef X
+        return false;
+    }
+#define X(C, W) \
+    if (cx == C && wl == W) return true;
+    CH_WIDE_SHAPES(X)
+#undef X
+    return false;
+}
+
+// Lines longer than one wavefront (a.P > 64).  units == 0 selects the split
+// form: the RHS tile pass, then (unless only diagnostics are asked for) the
+// x-solve in place on W.  With events, ev0 and ev1 bracket both launches.
+template <typename T>
+static hipError_t launch_wide(int cx, int units, const PassAArgs& a, size_t lds, hipStream_t s,
+                              hipEvent_t ev0, hipEvent_t ev1)
+{
+    const int wl = a.P / 64;
+    if (a.P % 64 || !passA_wide_has(sizeof(T) == 8 ? 0 : 1, cx, wl, units == 0)) return hipErrorInvalidValue;
+    if (units != 0) {
+#define X(C, W) \
+    if (cx == C && wl == W) return launchW<T, C, W, false>(a, lds, s, ev0, ev1);
+        CH_WIDE_SHAPES(X)
+#undef X
+        return hipErrorInvalidValue;
+    }
+    if constexpr (sizeof(T) == 8) {
+        hipError_t e;
+        if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
+        PassAArgs t = a;
+        t.blocks_per_member = (int64_t)(a.nx / kTileX) * ((a.ny + kTileY - 1) / kTileY);
+        t.nblocks = t.blocks_per_member * a.nmem;
+        if ((e = launch_k(rhs_tile_kernel<T>, (unsigned)t.nblocks, kPassAThreads, 0, s, t, nullptr, nullptr)) !=
+            hipSuccess)
+            return e;
+        if (a.mode != MODE_DIAG) {
+            e = hipErrorInvalidValue;
+#define X(C, W) \
+    if (cx == C && wl == W) e = launchW<T, C, W, true>(a, lds, s, nullptr, nullptr);
+            CH_SPLIT_SHAPES(X)
+#undef X
+            if (e != hipSuccess) return e;
+        }
+        if (ev1 && (e = hipEventRecord(ev1, s)) != hipSuccess) return e;
+        return hipSuccess;
+    }
+    return hipErrorInvalidValue;
+}
+
 int passA_pad(int prec) { return prec == 0 ? PadOf<double>::v : PadOf<float>::v; }
 int passA_halo(int prec) { return prec == 0 ? Vec16<double>::n : Vec16<float>::n; }
 
@@ -1667,6 +2124,11 @@ hipError_t launch_passA(int prec, int dim, int cx, int rl, int units, const Pass
                         size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (a.nblocks <= 0) return hipSuccess;
+    if (a.P > 64) {
+        if (dim != 2 || rl != 1 || a.cn) return hipErrorInvalidValue;
+        return prec == 0 ? launch_wide<double>(cx, units, a, lds, s, ev0, ev1)
+                         : launch_wide<float>(cx, units, a, lds, s, ev0, ev1);
+    }
     if (prec == 0)
         return dim == 2 ? launchA_shape<double, 2>(cx, rl, units, a, lds, s, ev0, ev1)
                         : launchA_shape<double, 3>(cx, rl, units, a, lds, s, ev0, ev1);

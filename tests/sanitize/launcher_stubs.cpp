@@ -39,6 +39,11 @@ bool passA_has(int dim, int cx, int rl, int units, bool cn)
     const bool c = cx == 4 || cx == 8 || cx == 16 || cx == 32 || cx == 64;
     return (dim == 2 || dim == 3) && c && rl >= 1 && units >= 1 && (!cn || (dim == 2 && units == 1));
 }
+bool passA_wide_has(int prec, int cx, int wl, bool split)
+{
+    if (split) return prec == 0 && wl == 4 && (cx == 4 || cx == 32);
+    return (wl == 2 && (cx == 8 || cx == 16 || cx == 32)) || (wl == 4 && (cx == 4 || cx == 8 || cx == 16 || cx == 32));
+}
 bool col_has(int prec, int cy) { return cy == 4 || cy == 8 || cy == 16 || cy == 32 || (prec == 1 && cy == 64); }
 int passA_pad(int) { return 1; }
 int passA_halo(int prec) { return prec == 0 ? 2 : 4; }

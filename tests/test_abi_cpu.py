@@ -58,6 +58,24 @@ def test_workspace_bytes_rejects(kw, frag):
     assert frag in str(e.value)
 
 
+@pytest.mark.parametrize("n,prec", [((8192, 8192), ch.CH_F64), ((8192, 64), ch.CH_F32_BULK),
+                                    ((64, 8192), ch.CH_F64), ((2048, 1024), ch.CH_F64),
+                                    ((16, 8192, 8), ch.CH_F64)])
+def test_workspace_bytes_accepts_long_lines(n, prec):
+    """x-lines beyond 64 chunks (2D) and columns of up to 256 chunks."""
+    sites = int(np.prod(n))
+    assert ch.ch_workspace_bytes([_desc(n=n)], prec, 10, 2) > 2 * sites * (8 if prec == ch.CH_F64 else 4)
+
+
+@pytest.mark.parametrize("n", [(8192, 16, 8), (6144, 64), (16384, 8), (64, 16384)])
+def test_workspace_bytes_rejects_lines_without_a_shape(n):
+    # 3D x-lines stay within one wavefront (n <= 4096); 6144 = 64 * 4 * 24 has
+    # no compiled chunk length; 16384 exceeds both line forms
+    with pytest.raises(ch.ChError) as e:
+        ch.ch_workspace_bytes([_desc(n=n)])
+    assert "unsupported" in str(e.value)
+
+
 def test_workspace_bytes_rejects_global_args():
     lib = ch.load()
     arr = ch.desc_array([_desc()])
