@@ -40,6 +40,7 @@ constexpr size_t kLdsLimit = 160 * 1024 - 1024;  // gfx950: 160 KiB per workgrou
 constexpr int kMaxStreams = 4;
 constexpr int kMaxHistBins = 4096;
 constexpr int kMinSplit = 4;
+constexpr int64_t kMaxBlocks = (int64_t)1 << 31;  // kernels index blocks in 32 bits
 
 size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 
@@ -116,7 +117,7 @@ bool planA_wide(ClassPlan& c, int prec, int cx, int rl, int waves, int units)
     c.bpmA = c.bands;
     c.bpmP = split ? split_tiles(c.nx, c.ny) : c.bpmA;
     c.nblocksA = class_size(c) * c.bpmA;
-    return true;
+    return c.nblocksA < kMaxBlocks && class_size(c) * c.bpmP < kMaxBlocks;
 }
 
 bool planA(ClassPlan& c, int prec, int cx, int rl, int waves, int units)
@@ -162,7 +163,7 @@ bool planA(ClassPlan& c, int prec, int cx, int rl, int waves, int units)
         c.bpmA = (int64_t)c.bands * ((c.nz + units - 1) / units);
     c.bpmP = c.bpmA;
     c.nblocksA = class_size(c) * c.bpmA;
-    return true;
+    return c.nblocksA < kMaxBlocks;
 }
 
 bool planCol(ClassPlan& c, int prec, int axis, int cy, int b)
@@ -190,7 +191,7 @@ bool planCol(ClassPlan& c, int prec, int axis, int cy, int b)
         p.outer = run;
     }
     p.nblocks = class_size(c) * (p.cols / b);
-    return true;
+    return p.nblocks < kMaxBlocks;
 }
 
 bool default_A(ClassPlan& c, int prec)
@@ -718,9 +719,11 @@ hipError_t enqueue_steps(ch_ctx* ctx, int64_t nsteps)
         for (hipStream_t s : ctx->aux)
             if ((e = hipStreamWaitEvent(s, ctx->ev_fork, 0)) != hipSuccess) return e;
     }
-    for (int ci = 0; ci < nc; ++ci) {
-        hipStream_t s = (ci % ns == 0) ? ctx->stream : ctx->aux[ci % ns - 1];
-        for (int64_t i = 0; i < nsteps; ++i) {
+    // step-major order: the launches (and a captured graph's nodes) of the
+    // classes interleave, so every stream has work from the first step on
+    for (int64_t i = 0; i < nsteps; ++i) {
+        for (int ci = 0; ci < nc; ++ci) {
+            hipStream_t s = (ci % ns == 0) ? ctx->stream : ctx->aux[ci % ns - 1];
             if ((e = launch_A(ctx, ci, MODE_STEP, nullptr, nullptr, s)) != hipSuccess) return e;
             if ((e = launch_cols(ctx, ci, 1, nullptr, nullptr, s)) != hipSuccess) return e;
             if (ctx->classes[ci].dim == 3 && (e = launch_cols(ctx, ci, 2, nullptr, nullptr, s)) != hipSuccess)
@@ -749,10 +752,10 @@ hipError_t enqueue_timing_steps(ch_ctx* ctx, int nsteps)
         for (hipStream_t s : ctx->aux)
             if ((e = hipStreamWaitEvent(s, ctx->ev_fork, 0)) != hipSuccess) return e;
     }
-    for (int ci = 0; ci < nc; ++ci) {
-        hipStream_t s = (ci % ns == 0) ? ctx->stream : ctx->aux[ci % ns - 1];
-        const ClassPlan& c = ctx->classes[ci];
-        for (int i = 0; i < nsteps; ++i) {
+    for (int i = 0; i < nsteps; ++i) {
+        for (int ci = 0; ci < nc; ++ci) {
+            hipStream_t s = (ci % ns == 0) ? ctx->stream : ctx->aux[ci % ns - 1];
+            const ClassPlan& c = ctx->classes[ci];
             if ((e = launch_A(ctx, ci, MODE_TIMING, nullptr, nullptr, s)) != hipSuccess) return e;
             for (int axis = 1; axis < c.dim; ++axis)
                 if ((e = launch_col(ctx->prec, c.col[axis].cy, col_args(ctx, ci, axis, W, W, false), s)) !=

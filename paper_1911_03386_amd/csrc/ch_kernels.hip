@@ -59,13 +59,22 @@ namespace chk {
 // --------------------------------------------------------------------------
 // helpers
 // --------------------------------------------------------------------------
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb)
 {
     // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
     // contiguous range of logical tiles so that neighbouring tiles (which share
     // halo rows and planes) hit the same L2.  A bijection for any nb.
-    int64_t q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+    // Block indices are 32-bit throughout (grids stay below 2^31 blocks, which
+    // the planner checks): 64-bit divisions expand to long scalar sequences
+    // that delay a block's first loads.
+    const uint32_t q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
     return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// lane / P for the lanes of a line group (P a power of two in most plans)
+__device__ __forceinline__ int lane_div(int lane, int P)
+{
+    return (P & (P - 1)) == 0 ? lane >> __builtin_ctz((unsigned)P) : lane / P;
 }
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
@@ -741,12 +750,12 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
 
-    const int64_t blk = xcd_remap(blockIdx.x, a.nblocks);
-    const int64_t per_member = (int64_t)a.bands_y * nz;
+    const uint32_t blk = xcd_remap(blockIdx.x, (uint32_t)a.nblocks);
+    const uint32_t per_member = (uint32_t)a.bands_y * (uint32_t)nz;
     const int mloc = (int)(blk / per_member);
-    const int64_t rem = blk - (int64_t)mloc * per_member;
-    const int z = (int)(rem / a.bands_y);
-    const int y0 = (int)(rem - (int64_t)z * a.bands_y) * a.R;
+    const uint32_t rem = blk - (uint32_t)mloc * per_member;
+    const int z = (int)(rem / (uint32_t)a.bands_y);
+    const int y0 = (int)(rem - (uint32_t)z * (uint32_t)a.bands_y) * a.R;
     const int mid = a.mids[mloc];
     const MemberDev& md = a.mem[mid];
     const T* C = reinterpret_cast<const T*>(a.C) + md.off;
@@ -786,7 +795,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     // sharing rows between the RL lines of a lane saves stencil work, and the
     // RL independent recursions interleave.
     const int P = a.P;
-    const int g = lane / P;                   // line group within the wavefront
+    const int g = lane_div(lane, P);          // line group within the wavefront
     const int j = lane - g * P;               // chunk index along the line
     const int groups = a.rows_per_wave / RL;  // line groups per wavefront
     const int rl0 = (wave * groups + g) * RL; // first x-line of this lane in the block
@@ -923,9 +932,9 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
             s1 += red[w][1];
             s2 += red[w][2];
         }
-        a.partials[blk * 3 + 0] = s0;
-        a.partials[blk * 3 + 1] = s1;
-        a.partials[blk * 3 + 2] = s2;
+        a.partials[(size_t)blk * 3 + 0] = s0;
+        a.partials[(size_t)blk * 3 + 1] = s1;
+        a.partials[(size_t)blk * 3 + 2] = s2;
     }
 }
 
@@ -962,9 +971,9 @@ __global__ void __launch_bounds__(kPassAThreads) passA_wide_kernel(PassAArgs a)
     const int li = wv / WL, wl = wv - li * WL;  // line of the block, wavefront within the line
     const int nx = a.nx, ny = a.ny;
 
-    const int64_t blk = xcd_remap(blockIdx.x, a.nblocks);
-    const int mloc = (int)(blk / a.bands_y);
-    const int y0 = (int)(blk - (int64_t)mloc * a.bands_y) * R;
+    const uint32_t blk = xcd_remap(blockIdx.x, (uint32_t)a.nblocks);
+    const int mloc = (int)(blk / (uint32_t)a.bands_y);
+    const int y0 = (int)(blk - (uint32_t)mloc * (uint32_t)a.bands_y) * R;
     const MemberDev& md = a.mem[a.mids[mloc]];
     const uint32_t bytes = (uint32_t)(md.sites * (int64_t)sizeof(T));
     T* Wout = reinterpret_cast<T*>(a.W) + md.off;
@@ -1162,9 +1171,9 @@ __global__ void __launch_bounds__(kPassAThreads) passA_wide_kernel(PassAArgs a)
                 s1 += red[w][1];
                 s2 += red[w][2];
             }
-            a.partials[blk * 3 + 0] = s0;
-            a.partials[blk * 3 + 1] = s1;
-            a.partials[blk * 3 + 2] = s2;
+            a.partials[(size_t)blk * 3 + 0] = s0;
+            a.partials[(size_t)blk * 3 + 1] = s1;
+            a.partials[(size_t)blk * 3 + 2] = s2;
         }
     }
 }
@@ -1193,10 +1202,10 @@ __global__ void __launch_bounds__(kPassAThreads) rhs_tile_kernel(PassAArgs a)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nx = a.nx, ny = a.ny;
     const int tiles_x = nx / TX;
-    const int64_t per_member = (int64_t)tiles_x * ((ny + TY - 1) / TY);
-    const int64_t blk = xcd_remap(blockIdx.x, a.nblocks);
+    const uint32_t per_member = (uint32_t)tiles_x * (uint32_t)((ny + TY - 1) / TY);
+    const uint32_t blk = xcd_remap(blockIdx.x, (uint32_t)a.nblocks);
     const int mloc = (int)(blk / per_member);
-    const int t = (int)(blk - (int64_t)mloc * per_member);
+    const int t = (int)(blk - (uint32_t)mloc * per_member);
     const int y0 = (t / tiles_x) * TY, x0 = (t % tiles_x) * TX;
     const MemberDev& md = a.mem[a.mids[mloc]];
     const uint32_t bytes = (uint32_t)(md.sites * (int64_t)sizeof(T));
@@ -1267,9 +1276,9 @@ __global__ void __launch_bounds__(kPassAThreads) rhs_tile_kernel(PassAArgs a)
             s1 += red[w][1];
             s2 += red[w][2];
         }
-        a.partials[blk * 3 + 0] = s0;
-        a.partials[blk * 3 + 1] = s1;
-        a.partials[blk * 3 + 2] = s2;
+        a.partials[(size_t)blk * 3 + 0] = s0;
+        a.partials[(size_t)blk * 3 + 1] = s1;
+        a.partials[(size_t)blk * 3 + 2] = s2;
     }
 }
 
@@ -1303,13 +1312,13 @@ __global__ void __launch_bounds__(kPassAThreads) passA_multi_kernel(PassAArgs a)
     const int nthreads = blockDim.x;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
 
-    const int64_t blk = xcd_remap(blockIdx.x, a.nblocks);
-    const int64_t bpm = a.blocks_per_member;
+    const uint32_t blk = xcd_remap(blockIdx.x, (uint32_t)a.nblocks);
+    const uint32_t bpm = (uint32_t)a.blocks_per_member;
     const int mloc = (int)(blk / bpm);
-    const int64_t rem = blk - (int64_t)mloc * bpm;
+    const uint32_t rem = blk - (uint32_t)mloc * bpm;
     // 2D: bands band0 .. band0 + nunits - 1;  3D: planes zbase .. zbase + nunits - 1 of band0
     const int band0 = (DIM == 2) ? (int)rem * a.units : (int)(rem % a.bands_y);
-    const int zbase = (DIM == 2) ? 0 : (int)(rem / a.bands_y) * a.units;
+    const int zbase = (DIM == 2) ? 0 : (int)(rem / (uint32_t)a.bands_y) * a.units;
     const int nunits = (DIM == 2) ? min(a.units, a.bands_y - band0) : min(a.units, nz - zbase);
     const int mid = a.mids[mloc];
     const MemberDev& md = a.mem[mid];
@@ -1409,7 +1418,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_multi_kernel(PassAArgs a)
     __syncthreads();
 
     const int P = a.P;
-    const int g = lane / P;
+    const int g = lane_div(lane, P);
     const int j = lane - g * P;
     const int groups = a.rows_per_wave / RL;
     const int rl0 = (wave * groups + g) * RL;
@@ -1640,9 +1649,9 @@ __global__ void __launch_bounds__(kPassAThreads) passA_multi_kernel(PassAArgs a)
                 s1 += red[w][1];
                 s2 += red[w][2];
             }
-            a.partials[blk * 3 + 0] = s0;
-            a.partials[blk * 3 + 1] = s1;
-            a.partials[blk * 3 + 2] = s2;
+            a.partials[(size_t)blk * 3 + 0] = s0;
+            a.partials[(size_t)blk * 3 + 1] = s1;
+            a.partials[(size_t)blk * 3 + 2] = s2;
         }
     }
 }
@@ -1670,14 +1679,14 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
     const bool colok = j0 < P;
     const int j = colok ? j0 : 0;
     const int c = tid & (a.b - 1);
-    const int64_t blk = xcd_remap(blockIdx.x, a.nblocks);
-    const int64_t bpm = a.cols >> a.bshift;
+    const uint32_t blk = xcd_remap(blockIdx.x, (uint32_t)a.nblocks);
+    const uint32_t bpm = (uint32_t)(a.cols >> a.bshift);
     const int mloc = (int)(blk / bpm);
     // the block's b columns are consecutive elements of one run (b divides the
     // run length): its first column's element offset is block-uniform
-    const int64_t col0 = (blk - (int64_t)mloc * bpm) << a.bshift;
-    const int64_t run = col0 / a.run;
-    const int64_t base0 = (col0 - run * a.run) + run * a.outer;
+    const uint32_t col0 = (blk - (uint32_t)mloc * bpm) << a.bshift;
+    const uint32_t run = col0 / (uint32_t)a.run;
+    const int64_t base0 = (int64_t)(col0 - run * (uint32_t)a.run) + (int64_t)run * a.outer;
     const MemberDev& md = a.mem[a.mids[mloc]];
     const int64_t st = a.stride;
     // lane offset: column c, first element of chunk j; element k of the chunk

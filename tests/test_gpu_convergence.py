@@ -65,3 +65,12 @@ def test_convergence_table_and_first_order():
               "paper", table.get(r["n"]))
         assert abs(r["E_average"] / table[r["n"]] - 1) <= 0.15, r
     assert 0.8 <= rows[-2]["order_average"] <= 1.3
+
+
+def test_convergence_e4096_against_the_table():
+    """Appendix A, Table tab:cvg: E_4096, the 4096^2 grid (65190 steps of
+    16.7 M sites) against the 2048^2 one, to 15 % with 2 x 2 averaging."""
+    table = _paper_table()
+    (r,) = conv.study([2048, 4096])
+    print({k: round(v, 7) if isinstance(v, float) else v for k, v in r.items()}, "paper", table[4096])
+    assert abs(r["E_average"] / table[4096] - 1) <= 0.15, r
