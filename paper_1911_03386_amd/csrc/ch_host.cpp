@@ -592,6 +592,23 @@ ch_status upload_tables(ch_ctx* ctx)
     return CH_OK;
 }
 
+// The class's members as one arithmetic run (consecutive ids at equally
+// spaced offsets), or mid0 = -1.
+MemberRun member_run(const ch_ctx* ctx, const ClassPlan& c)
+{
+    MemberRun r{-1, 0, 0};
+    const auto& mv = c.members;
+    if (mv.empty()) return r;
+    const int64_t off0 = ctx->L.moff[mv[0]];
+    const int64_t stride = mv.size() > 1 ? ctx->L.moff[mv[1]] - off0 : 0;
+    for (size_t i = 0; i < mv.size(); ++i)
+        if (mv[i] != mv[0] + (int)i || ctx->L.moff[mv[i]] != off0 + (int64_t)i * stride) return r;
+    r.mid0 = mv[0];
+    r.off0 = off0;
+    r.stride = stride;
+    return r;
+}
+
 PassAArgs passA_args(ch_ctx* ctx, int ci, int mode)
 {
     ClassPlan& c = ctx->classes[ci];
@@ -601,6 +618,7 @@ PassAArgs passA_args(ch_ctx* ctx, int ci, int mode)
     a.mem = ctx->d_mem();
     a.mids = reinterpret_cast<const int32_t*>(ctx->ws + c.off_mids);
     a.nmem = (int32_t)c.members.size();
+    a.run = member_run(ctx, c);
     a.nx = c.nx;
     a.ny = c.ny;
     a.nz = c.nz;
@@ -654,12 +672,14 @@ ColArgs col_args(ch_ctx* ctx, int ci, int axis, const void* src, void* dst, bool
     a.dst = dst;
     a.mem = ctx->d_mem();
     a.mids = reinterpret_cast<const int32_t*>(ctx->ws + c.off_mids);
+    a.mrun = member_run(ctx, c);
     a.axis = axis;
     a.n = axis == 1 ? c.ny : c.nz;
     a.stride = p.stride;
     a.run = p.run;
     a.outer = p.outer;
     a.cols = p.cols;
+    a.msites = (int64_t)c.nx * c.ny * c.nz;
     a.b = p.b;
     a.bshift = __builtin_ctz((unsigned)p.b);
     a.P = p.P;
@@ -1820,6 +1840,7 @@ ch_status ch_step_static(const ch_member_desc* members, int32_t m, ch_precision 
     a.mem = reinterpret_cast<const MemberDev*>(base + S.mem);
     a.mids = reinterpret_cast<const int32_t*>(base + S.mids);
     a.nmem = m;
+    a.run = MemberRun{0, 0, sites};  // members i at i * sites
     a.nx = c.nx;
     a.ny = c.ny;
     a.nz = c.nz;
@@ -1860,6 +1881,8 @@ ch_status ch_step_static(const ch_member_desc* members, int32_t m, ch_precision 
         ca.dst = dst;
         ca.mem = a.mem;
         ca.mids = a.mids;
+        ca.mrun = a.run;
+        ca.msites = sites;
         ca.axis = axis;
         ca.n = axis == 1 ? c.ny : c.nz;
         ca.stride = p.stride;

@@ -44,6 +44,16 @@ struct MemberDev {
     AxisCoef ax[3];
 };
 
+// A class whose members have consecutive ids (every class of a uniform
+// ensemble) is also described arithmetically: member mloc is id mid0 + mloc
+// at element offset off0 + mloc * stride.  Kernels then form a member's
+// buffer without a dependent load of the member tables.  mid0 < 0: look the
+// members up.
+struct MemberRun {
+    int32_t mid0 = -1;
+    int64_t off0 = 0, stride = 0;
+};
+
 // Step kernel modes.
 enum : int { MODE_STEP = 0, MODE_DIAG = 1, MODE_TIMING = 2 };
 
@@ -78,6 +88,7 @@ struct PassAArgs {
     const MemberDev* mem;      // member table (global ids)
     const int32_t* mids;       // member ids of this class
     int32_t nmem;              // members in this class
+    MemberRun run;             // the class's members as one arithmetic run, where they are
     int32_t nx, ny, nz;
     int32_t P;                 // chunks per x-line (lanes; above 64 a line spans P / 64 wavefronts)
     int32_t rows_per_wave;     // x-lines per wavefront (line groups x lines per lane; 0 above 64 chunks)
@@ -102,12 +113,14 @@ struct ColArgs {
     void* dst;                 // T* (may equal src)
     const MemberDev* mem;
     const int32_t* mids;
+    MemberRun mrun;            // the class's members as one arithmetic run, where they are
     int32_t axis;              // 1 = y, 2 = z
     int32_t n;                 // line length
     int64_t stride;            // element distance between line neighbours
     int64_t run;               // columns come in runs of `run` consecutive elements
     int64_t outer;             // element distance between runs
     int64_t cols;              // columns per member
+    int64_t msites;            // sites per member
     int32_t b;                 // columns per block (a power of two dividing run)
     int32_t bshift;            // log2 b
     int32_t P;                 // chunks per column

@@ -71,6 +71,18 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb)
     return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// Member id and element offset of class member mloc: arithmetic for a run of
+// consecutive members, else from the member tables.
+__device__ __forceinline__ int member_id(const MemberRun& r, const int32_t* mids, int mloc)
+{
+    return r.mid0 >= 0 ? r.mid0 + mloc : mids[mloc];
+}
+__device__ __forceinline__ int64_t member_off(const MemberRun& r, const MemberDev* mem, int mid, int mloc)
+{
+    if (r.mid0 >= 0) return r.off0 + (int64_t)mloc * r.stride;
+    return mem[mid].off;
+}
+
 // lane / P for the lanes of a line group (P a power of two in most plans)
 __device__ __forceinline__ int lane_div(int lane, int P)
 {
@@ -329,6 +341,16 @@ __device__ __forceinline__ void scan_bwd_wave(T (&e0)[RL], T (&e1)[RL], int j, i
     }
 }
 
+// Diagnostics step n needs (n >= 0): F at n = jK - 1, jK, jK + 1 (the centred
+// difference of eq. (dFdt)) and the gradient of mu at n = jK.  One remainder,
+// in 32 bits while n fits.
+__device__ __forceinline__ void step_needs(int64_t n, int K, bool& needF, bool& needG)
+{
+    const int r = (n < 0x7fffffff) ? (int)((uint32_t)n % (uint32_t)K) : (int)(n % K);
+    needG = r == 0;
+    needF = needG || (n >= 1 && r == 1) || r == K - 1;
+}
+
 // Per-member reduction of the pass-A partials into the series.  Each thread of
 // the block sums a strided subset of the member's partials (Neumaier), the
 // wavefronts reduce with a fixed shuffle tree and thread 0 combines the
@@ -340,10 +362,7 @@ __device__ void finalize_block(const FinArgs& f, int b, int G, double (*sred)[3]
     const int64_t n = *f.nstamp;
     const int K = f.K;
     bool needF = true, needG = true;
-    if (f.mode == MODE_STEP) {
-        needG = (n % K) == 0;
-        needF = needG || (n >= 1 && ((n - 1) % K) == 0) || (((n + 1) % K) == 0);
-    }
+    if (f.mode == MODE_STEP) step_needs(n, K, needF, needG);
     if (!needF) return;
     for (int ml = b; ml < f.nmem; ml += G) {
         double s[3] = {0.0, 0.0, 0.0}, cmp[3] = {0.0, 0.0, 0.0};
@@ -491,8 +510,40 @@ __device__ __forceinline__ void stage_rows(T* sC, __amdgpu_buffer_rsrc_t rC, int
     const int nvec = nx / VEC;
     const int nrows_all = npl * nrows;
     const int nseg = (nvec + 63) >> 6;
-    {
-        constexpr int NB = 8;
+    constexpr int NB = 8;
+    if constexpr (DIM == 2) {
+        // one plane: the wavefront's rows are wv, wv + nwaves, ...
+        int r = wv, seg = 0;  // wave-uniform cursor (row, segment)
+        while (r < nrows) {
+            VT val[NB];
+            int dst[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                dst[i] = -1;
+                if (r < nrows) {
+                    const int rowo = wrapi(y0 - ylo + r, ny) * nx;  // wave-uniform
+                    const int xi = seg * 64 + lane;
+                    if (xi < nvec) {
+                        const uint32_t xs = (uint32_t)xi * VEC, xx = xs + HALO;
+                        val[i] = buf_load16<VT>(rC, (int)xs * (int)sizeof(T), rowo * (int)sizeof(T));
+                        dst[i] = r * pitch + (int)(xx + xx / CX * PADE);
+                    }
+                    if (++seg == nseg) {
+                        seg = 0;
+                        r += nwaves;
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+                if (dst[i] >= 0) {
+                    T e[VEC];
+                    vec_get<T>(val[i], e);
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) sC[dst[i] + q] = e[q];
+                }
+        }
+    } else {
         int pl = 0, r = wv, seg = 0;  // wave-uniform cursor (plane, row, segment)
         while (r >= nrows) {
             r -= nrows;
@@ -533,6 +584,8 @@ __device__ __forceinline__ void stage_rows(T* sC, __amdgpu_buffer_rsrc_t rC, int
                     for (int q = 0; q < VEC; ++q) sC[dst[i] + q] = e[q];
                 }
         }
+    }
+    {
         if (halos)
             for (int h = tid; h < 2 * nrows_all; h += nthreads) {
                 const int rid = h >> 1, pl = rid / nrows, r = rid - pl * nrows;
@@ -756,22 +809,19 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     const uint32_t rem = blk - (uint32_t)mloc * per_member;
     const int z = (int)(rem / (uint32_t)a.bands_y);
     const int y0 = (int)(rem - (uint32_t)z * (uint32_t)a.bands_y) * a.R;
-    const int mid = a.mids[mloc];
+    const int mid = member_id(a.run, a.mids, mloc);
     const MemberDev& md = a.mem[mid];
-    const T* C = reinterpret_cast<const T*>(a.C) + md.off;
-    T* Wout = reinterpret_cast<T*>(a.W) + md.off;
+    const int64_t moff = member_off(a.run, a.mem, mid, mloc);
+    const uint32_t bytes = (uint32_t)((int64_t)nx * ny * nz * (int64_t)sizeof(T));
+    const T* C = reinterpret_cast<const T*>(a.C) + moff;
+    T* Wout = reinterpret_cast<T*>(a.W) + moff;
     // the member's field as a buffer: rows are wave-uniform scalar offsets
-    const __amdgpu_buffer_rsrc_t rC = buffer_of(C, (uint32_t)(md.sites * (int64_t)sizeof(T)));
+    const __amdgpu_buffer_rsrc_t rC = buffer_of(C, bytes);
 
     const int64_t n = *a.step;
     const int K = a.K;
-    bool needF = false, needG = false;
-    if (a.mode == MODE_STEP) {
-        needG = (n % K) == 0;
-        needF = needG || (n >= 1 && ((n - 1) % K) == 0) || (((n + 1) % K) == 0);
-    } else if (a.mode == MODE_DIAG) {
-        needF = needG = true;
-    }
+    bool needF = a.mode == MODE_DIAG, needG = a.mode == MODE_DIAG;
+    if (a.mode == MODE_STEP) step_needs(n, K, needF, needG);
     const bool solve = (a.mode != MODE_DIAG);
 
     // ---- stage C rows (with periodic halos) in LDS --------------------------
@@ -921,7 +971,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     // (the __syncthreads above ended every read of the staged rows)
     if (solve)
         write_back<T, CX, RL>(sC + pitch, pitch, v, rowok, rl0, j, wv, lane, a.rows_per_wave, Ract, nvec,
-                              buffer_of(Wout, (uint32_t)(md.sites * (int64_t)sizeof(T))), (z * ny + y0) * nx, nx);
+                              buffer_of(Wout, bytes), (z * ny + y0) * nx, nx);
 
     // ---- block partials of F, sum C, sum |grad mu|^2 (reduced by finalize) ----
     if (blk == 0 && tid == 0 && a.mode != MODE_TIMING) *a.nstamp = n;
@@ -974,22 +1024,17 @@ __global__ void __launch_bounds__(kPassAThreads) passA_wide_kernel(PassAArgs a)
     const uint32_t blk = xcd_remap(blockIdx.x, (uint32_t)a.nblocks);
     const int mloc = (int)(blk / (uint32_t)a.bands_y);
     const int y0 = (int)(blk - (uint32_t)mloc * (uint32_t)a.bands_y) * R;
-    const MemberDev& md = a.mem[a.mids[mloc]];
-    const uint32_t bytes = (uint32_t)(md.sites * (int64_t)sizeof(T));
-    T* Wout = reinterpret_cast<T*>(a.W) + md.off;
-    const T* src = XONLY ? Wout : reinterpret_cast<const T*>(a.C) + md.off;
+    const int mid = member_id(a.run, a.mids, mloc);
+    const MemberDev& md = a.mem[mid];
+    const int64_t moff = member_off(a.run, a.mem, mid, mloc);
+    const uint32_t bytes = (uint32_t)((int64_t)nx * ny * (int64_t)sizeof(T));
+    T* Wout = reinterpret_cast<T*>(a.W) + moff;
+    const T* src = XONLY ? Wout : reinterpret_cast<const T*>(a.C) + moff;
 
     const int64_t n = *a.step;
     const int K = a.K;
-    bool needF = false, needG = false;
-    if (!XONLY) {
-        if (a.mode == MODE_STEP) {
-            needG = (n % K) == 0;
-            needF = needG || (n >= 1 && ((n - 1) % K) == 0) || (((n + 1) % K) == 0);
-        } else if (a.mode == MODE_DIAG) {
-            needF = needG = true;
-        }
-    }
+    bool needF = !XONLY && a.mode == MODE_DIAG, needG = needF;
+    if (!XONLY && a.mode == MODE_STEP) step_needs(n, K, needF, needG);
     const bool solve = (a.mode != MODE_DIAG);
 
     constexpr int YLO = XONLY ? 0 : 1;
@@ -1207,19 +1252,16 @@ __global__ void __launch_bounds__(kPassAThreads) rhs_tile_kernel(PassAArgs a)
     const int mloc = (int)(blk / per_member);
     const int t = (int)(blk - (uint32_t)mloc * per_member);
     const int y0 = (t / tiles_x) * TY, x0 = (t % tiles_x) * TX;
-    const MemberDev& md = a.mem[a.mids[mloc]];
-    const uint32_t bytes = (uint32_t)(md.sites * (int64_t)sizeof(T));
-    const __amdgpu_buffer_rsrc_t rC = buffer_of(reinterpret_cast<const T*>(a.C) + md.off, bytes);
+    const int mid = member_id(a.run, a.mids, mloc);
+    const MemberDev& md = a.mem[mid];
+    const int64_t moff = member_off(a.run, a.mem, mid, mloc);
+    const uint32_t bytes = (uint32_t)((int64_t)nx * ny * (int64_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rC = buffer_of(reinterpret_cast<const T*>(a.C) + moff, bytes);
 
     const int64_t n = *a.step;
     const int K = a.K;
-    bool needF = false, needG = false;
-    if (a.mode == MODE_STEP) {
-        needG = (n % K) == 0;
-        needF = needG || (n >= 1 && ((n - 1) % K) == 0) || (((n + 1) % K) == 0);
-    } else if (a.mode == MODE_DIAG) {
-        needF = needG = true;
-    }
+    bool needF = a.mode == MODE_DIAG, needG = a.mode == MODE_DIAG;
+    if (a.mode == MODE_STEP) step_needs(n, K, needF, needG);
     const bool store = (a.mode != MODE_DIAG);
 
     // stage rows y0 - 1 .. y0 + Tact (+1 for the gradient of mu), periodic
@@ -1250,7 +1292,7 @@ __global__ void __launch_bounds__(kPassAThreads) rhs_tile_kernel(PassAArgs a)
         T v[CT];
 #pragma unroll
         for (int k = 0; k < CT; ++k) v[k] = rhs_site<T, 2>(at, 0, k + HALO, cdx, cdy, T(0), gxy, T(0), T(0));
-        const __amdgpu_buffer_rsrc_t rW = buffer_of(reinterpret_cast<T*>(a.W) + md.off, bytes);
+        const __amdgpu_buffer_rsrc_t rW = buffer_of(reinterpret_cast<T*>(a.W) + moff, bytes);
         const int o = ((y0 + row) * nx + x0 + jx * CT) * (int)sizeof(T);
 #pragma unroll
         for (int k = 0; k < CT; k += VEC) buf_store16<VT>(vec_make<T>(v + k), rW, o + k * (int)sizeof(T), 0);
@@ -1320,20 +1362,16 @@ __global__ void __launch_bounds__(kPassAThreads) passA_multi_kernel(PassAArgs a)
     const int band0 = (DIM == 2) ? (int)rem * a.units : (int)(rem % a.bands_y);
     const int zbase = (DIM == 2) ? 0 : (int)(rem / (uint32_t)a.bands_y) * a.units;
     const int nunits = (DIM == 2) ? min(a.units, a.bands_y - band0) : min(a.units, nz - zbase);
-    const int mid = a.mids[mloc];
+    const int mid = member_id(a.run, a.mids, mloc);
     const MemberDev& md = a.mem[mid];
-    const T* C = reinterpret_cast<const T*>(a.C) + md.off;
-    T* Wout = reinterpret_cast<T*>(a.W) + md.off;
+    const int64_t moff = member_off(a.run, a.mem, mid, mloc);
+    const T* C = reinterpret_cast<const T*>(a.C) + moff;
+    T* Wout = reinterpret_cast<T*>(a.W) + moff;
 
     const int64_t n = *a.step;
     const int K = a.K;
-    bool needF = false, needG = false;
-    if (a.mode == MODE_STEP) {
-        needG = (n % K) == 0;
-        needF = needG || (n >= 1 && ((n - 1) % K) == 0) || (((n + 1) % K) == 0);
-    } else if (a.mode == MODE_DIAG) {
-        needF = needG = true;
-    }
+    bool needF = a.mode == MODE_DIAG, needG = a.mode == MODE_DIAG;
+    if (a.mode == MODE_STEP) step_needs(n, K, needF, needG);
     const bool solve = (a.mode != MODE_DIAG);
 
     const int pitch = a.pitch;
@@ -1599,7 +1637,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_multi_kernel(PassAArgs a)
         if (DIM == 2 && solve) {
             __syncthreads();  // every read of the staged rows is done
             write_back<T, CX, RL>(sC + pitch, pitch, v, rowok, rl0, j, wv, lane, a.rows_per_wave, Ract, nvec,
-                                  buffer_of(Wout, (uint32_t)(md.sites * (int64_t)sizeof(T))), y0 * nx, nx);
+                                  buffer_of(Wout, (uint32_t)((int64_t)nx * ny * (int64_t)sizeof(T))), y0 * nx, nx);
         }
 
         if (has_next) {
@@ -1687,13 +1725,15 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
     const uint32_t col0 = (blk - (uint32_t)mloc * bpm) << a.bshift;
     const uint32_t run = col0 / (uint32_t)a.run;
     const int64_t base0 = (int64_t)(col0 - run * (uint32_t)a.run) + (int64_t)run * a.outer;
-    const MemberDev& md = a.mem[a.mids[mloc]];
+    const int mid = member_id(a.mrun, a.mids, mloc);
+    const MemberDev& md = a.mem[mid];
+    const int64_t moff = member_off(a.mrun, a.mem, mid, mloc);
     const int64_t st = a.stride;
     // lane offset: column c, first element of chunk j; element k of the chunk
     // adds the uniform k * stride
-    const uint32_t span = (uint32_t)((md.sites - base0) * (int64_t)sizeof(T));
-    const __amdgpu_buffer_rsrc_t rsrc = buffer_of(reinterpret_cast<const T*>(a.src) + md.off + base0, span);
-    const __amdgpu_buffer_rsrc_t rdst = buffer_of(reinterpret_cast<T*>(a.dst) + md.off + base0, span);
+    const uint32_t span = (uint32_t)((a.msites - base0) * (int64_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rsrc = buffer_of(reinterpret_cast<const T*>(a.src) + moff + base0, span);
+    const __amdgpu_buffer_rsrc_t rdst = buffer_of(reinterpret_cast<T*>(a.dst) + moff + base0, span);
     const int voff = (int)(((int64_t)j * CY * st + c) * (int64_t)sizeof(T));
     const int sstep = (int)(st * (int64_t)sizeof(T));
 
