@@ -11,7 +11,11 @@ Prints ONE JSON line.  Default workload: the FP32-bulk batched ensemble of
 64 x 512^2 grids; the same line carries the plain FP64 single 1024^2 grid and
 the FP64 64 x 512^2 ensemble measured the same way ("compare"), the roofline
 figures of the dominant kernel and the oracle timed on the host cores.  The
-timed steps are replays of a HIP graph captured and uploaded beforehand.
+timed steps are replays of a HIP graph captured and uploaded beforehand, or
+direct launches: before the warm-up, one untimed trial of each launch mode
+over min(steps, 64) steps picks the faster one for the timed region (graph
+replays start after a launch latency of about 0.3 ms; direct launches start
+at once, but their classes' streams may share hardware queues).
 
 `--workload model1` measures the droplet-population ensembles instead (Model 1
 of the paper): the whole table of Section 3 (100 populations for each N =
@@ -110,15 +114,30 @@ def run_gpu(wl, steps, warmup, kernel_steps, graph_steps, autotune, tune_cache):
 
     from paper_1911_03386_amd import Ensemble
 
-    total = warmup + steps + kernel_steps + 2
+    trial = min(steps, 64)
+    total = warmup + steps + kernel_steps + 4 * trial + 2
     ens = Ensemble(wl.descs, prec=wl.prec, cadence=wl.cadence, max_samples=total // wl.cadence + 2)
     if autotune:
         ens.autotune(tune_cache)
-    # the graph is captured, instantiated and uploaded here, before anything
-    # is timed (tuning drops it, so this comes after the tuning)
-    gs = graph_len(steps, graph_steps)
-    ens.set_graph_steps(gs)
     ens.init_random()
+    # launch mode: one trial of each over `trial` steps (after one untimed
+    # pass in that mode); graphs are captured, instantiated and uploaded by
+    # set_graph_steps, before anything is timed
+    gs = graph_len(steps, graph_steps)
+    trials = {}
+    for g in (gs, 0):
+        ens.set_graph_steps(graph_len(trial, g) if g else 0)
+        ens.step(trial)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(ens.stream)
+        ens.step(trial)
+        t1.record(ens.stream)
+        torch.cuda.synchronize()
+        trials["graph" if g else "direct"] = t0.elapsed_time(t1) / trial
+    mode = "graph" if trials["graph"] <= trials["direct"] else "direct"
+    ens.set_graph_steps(gs if mode == "graph" else 0)
     if warmup:
         ens.step(warmup)
     torch.cuda.synchronize()
@@ -136,8 +155,11 @@ def run_gpu(wl, steps, warmup, kernel_steps, graph_steps, autotune, tune_cache):
     plan = ens.describe()
     ens.close()
     return dict(wall=wall, gpu_ms=gpu_ms, kernel_ms=[float(x) for x in kms], plan=plan,
-                F=[float(x) for x in F[:4]], graph={"steps_per_graph": gs, "replays": steps // gs,
-                                                    "direct_steps": steps % gs})
+                F=[float(x) for x in F[:4]], graph={"launch": mode,
+                                                    "trial_ms_per_step": {k: round(v, 5) for k, v in trials.items()},
+                                                    "steps_per_graph": gs if mode == "graph" else 0,
+                                                    "replays": steps // gs if mode == "graph" else 0,
+                                                    "direct_steps": steps % gs if mode == "graph" else steps})
 
 
 def copy_calibration():
