@@ -606,17 +606,16 @@ __device__ __forceinline__ void stage_rows(T* sC, __amdgpu_buffer_rsrc_t rC, int
 
 // Per-lane partial sums of the diagnostics over the lane's chunk of its RL
 // lines (FP64): F (bulk + gradient energy, forward differences), sum C, and
-// sum |grad_h mu|^2 with mu = C^3 - C - gamma lap_h C.  cb points at the
-// lane's chunk in the staged rows (line rl0, chunk start); rows and planes of
-// the stencil are at +-pitch and +-planeStride.
-template <typename T, int DIM, int CX, int RL>
-__device__ __forceinline__ void diag_sums(const T* cb, int pitch, int planeStride, unsigned rowmask,
-                                          const MemberDev& md, int conv, bool needF, bool needG, double& pF,
-                                          double& pS, double& pG)
+// sum |grad_h mu|^2 with mu = C^3 - C - gamma lap_h C.  `at(dz, dy, m)`
+// reads the staged field at plane offset dz, line dy of the lane's lines and
+// element m of its chunk (the halo included); bit q of rowmask marks line q
+// as inside the grid.
+template <typename T, int DIM, int CX, int RL, typename At>
+__device__ __forceinline__ void diag_sums(const At& at, unsigned rowmask, const MemberDev& md, int conv,
+                                          bool needF, bool needG, double& pF, double& pS, double& pG)
 {
-    constexpr int PADE = PadOf<T>::v;
     constexpr int HALO = Vec16<T>::n;
-#define AT(dz, dy, m) cb[(dz) * planeStride + (dy) * pitch + (m) + ((m) / CX) * PADE]
+#define AT(dz, dy, m) at(dz, dy, m)
     if (needF) {
         const double cbulk = conv ? 0.5 : 0.25;
         const double hg = 0.5 * md.gamma;
@@ -897,7 +896,8 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
         unsigned rm = 0;
 #pragma unroll
         for (int q = 0; q < RL; ++q) rm |= rowok[q] ? (1u << q) : 0u;
-        diag_sums<T, DIM, CX, RL>(cb, pitch, planeStride, rm, md, a.conv, needF, needG, pF, pS, pG);
+        auto at = [&](int dz, int dy, int m) { return AT(dz, dy, m); };
+        diag_sums<T, DIM, CX, RL>(at, rm, md, a.conv, needF, needG, pF, pS, pG);
     }
 #undef AT
 
@@ -1064,7 +1064,10 @@ __global__ void __launch_bounds__(kPassAThreads) passA_wide_kernel(PassAArgs a)
         for (int k = 0; k < CX; ++k) v[0][k] = rhs_site<T, 2>(at, 0, k + HALO, cdx, cdy, T(0), gxy, T(0), T(0));
     }
     double pF = 0.0, pS = 0.0, pG = 0.0;
-    if (!XONLY && active) diag_sums<T, 2, CX, 1>(cb, pitch, 0, 1u, md, a.conv, needF, needG, pF, pS, pG);
+    if (!XONLY && active) {
+        auto at = [&](int, int dy, int m) { return cb[dy * pitch + m + (m / CX) * PADE]; };
+        diag_sums<T, 2, CX, 1>(at, 1u, md, a.conv, needF, needG, pF, pS, pG);
+    }
 
     // ---- x-line solves across the line's wavefronts ------------------------
     T mean = T(0);
@@ -1284,7 +1287,10 @@ __global__ void __launch_bounds__(kPassAThreads) rhs_tile_kernel(PassAArgs a)
     const bool ok = row < Tact;
     const T* cb = sT + (row + 1) * PITCH + jx * (CT + PADE);
     double pF = 0.0, pS = 0.0, pG = 0.0;
-    if (ok) diag_sums<T, 2, CT, 1>(cb, PITCH, 0, 1u, md, a.conv, needF, needG, pF, pS, pG);
+    if (ok) {
+        auto at = [&](int, int dy, int m) { return cb[dy * PITCH + m + (m / CT) * PADE]; };
+        diag_sums<T, 2, CT, 1>(at, 1u, md, a.conv, needF, needG, pF, pS, pG);
+    }
     if (store && ok) {
         const T cdx = (T)(md.dt * md.ih2[0]), cdy = (T)(md.dt * md.ih2[1]);
         const T gxy = (T)(2.0 * md.gamma * md.dt * md.ih2[0] * md.ih2[1]);
@@ -1526,59 +1532,11 @@ __global__ void __launch_bounds__(kPassAThreads) passA_multi_kernel(PassAArgs a)
                     v[q][k] = rhs_site<T, DIM>(at, q, k + HALO, cdx, cdy, cdz, gxy, gxz, gyz);
         }
         if (active) {
-            if (needF) {
-                const double cbulk = a.conv ? 0.5 : 0.25;
-                const double hg = 0.5 * md.gamma;
-                const double dx2 = md.ih2[0], dy2 = md.ih2[1], dz2 = md.ih2[2];
+            unsigned rm = 0;
 #pragma unroll
-                for (int q = 0; q < RL; ++q) {
-                    if (!rowok[q]) continue;
-#pragma unroll
-                    for (int k = 0; k < CX; ++k) {
-                        const int m0 = k + HALO;
-                        const double c = (double)AT(0, q, m0);
-                        const double ex = (double)AT(0, q, m0 + 1) - c;
-                        const double ey = (double)AT(0, q + 1, m0) - c;
-                        double gr = ex * ex * dx2 + ey * ey * dy2;
-                        if (DIM == 3) {
-                            const double ez = (double)AT(1, q, m0) - c;
-                            gr += ez * ez * dz2;
-                        }
-                        const double qq = c * c - 1.0;
-                        pF += cbulk * qq * qq + hg * gr;
-                        pS += c;
-                    }
-                }
-            }
-            if (needG) {
-                const double gam = md.gamma;
-                const double dx2 = md.ih2[0], dy2 = md.ih2[1], dz2 = md.ih2[2];
-                auto MU = [&](int dz, int dy, int m) -> double {
-                    const double uu = (double)AT(dz, dy, m);
-                    double l = ((double)AT(dz, dy, m + 1) - 2.0 * uu + (double)AT(dz, dy, m - 1)) * dx2 +
-                               ((double)AT(dz, dy + 1, m) - 2.0 * uu + (double)AT(dz, dy - 1, m)) * dy2;
-                    if (DIM == 3)
-                        l += ((double)AT(dz + 1, dy, m) - 2.0 * uu + (double)AT(dz - 1, dy, m)) * dz2;
-                    return uu * uu * uu - uu - gam * l;
-                };
-#pragma unroll
-                for (int q = 0; q < RL; ++q) {
-                    if (!rowok[q]) continue;
-#pragma unroll
-                    for (int k = 0; k < CX; ++k) {
-                        const int m0 = k + HALO;
-                        const double mu = MU(0, q, m0);
-                        const double gx = MU(0, q, m0 + 1) - mu;
-                        const double gy = MU(0, q + 1, m0) - mu;
-                        double qq = gx * gx * dx2 + gy * gy * dy2;
-                        if (DIM == 3) {
-                            const double gz = MU(1, q, m0) - mu;
-                            qq += gz * gz * dz2;
-                        }
-                        pG += qq;
-                    }
-                }
-            }
+            for (int q = 0; q < RL; ++q) rm |= rowok[q] ? (1u << q) : 0u;
+            auto at = [&](int dz, int dy, int m) { return AT(dz, dy, m); };
+            diag_sums<T, DIM, CX, RL>(at, rm, md, a.conv, needF, needG, pF, pS, pG);
         }
 #undef AT
 
