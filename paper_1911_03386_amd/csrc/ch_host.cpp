@@ -567,7 +567,35 @@ void fill_member(const ch_member_desc& d, int64_t off, const ClassPlan& c, int p
         const double rho = theta * d.gamma * d.dt / (h2 * h2);  // the solves are (I + theta gamma dt D^2)
         const int chunk = a == 0 ? c.cx : c.col[a].cy;
         axis_coef(rho, d.n[a], chunk, prec, md.ax[a]);
+        const AxisCoef& x = md.ax[a];
+        AxisCoefF& f = md.axf[a];
+        f.a1 = (float)x.a1;
+        f.a2 = (float)x.a2;
+        f.ikappa = (float)x.ikappa;
+        f.inv_n = (float)x.inv_n;
+        for (int i = 0; i < 2; ++i) f.E1[i] = (float)x.E1[i];
+        for (int i = 0; i < 4; ++i) {
+            f.M[i] = (float)x.M[i];
+            f.W[i] = (float)x.W[i];
+            for (int l = 0; l < kMaxScanLevels; ++l) f.Mp[l][i] = (float)x.Mp[l][i];
+        }
     }
+    const double* ih2 = md.ih2;
+    double* rc = md.rc;
+    rc[RC_DX] = md.dt * ih2[0];
+    rc[RC_DY] = md.dt * ih2[1];
+    rc[RC_DZ] = md.dt * ih2[2];
+    rc[RC_GXY] = 2.0 * md.gamma * md.dt * ih2[0] * ih2[1];
+    rc[RC_GXZ] = 2.0 * md.gamma * md.dt * ih2[0] * ih2[2];
+    rc[RC_GYZ] = 2.0 * md.gamma * md.dt * ih2[1] * ih2[2];
+    rc[RC_AX4] = md.gamma * md.dt * ih2[0] * ih2[0];
+    rc[RC_AY4] = md.gamma * md.dt * ih2[1] * ih2[1];
+    rc[RC_IHX2] = ih2[0];
+    rc[RC_IHY2] = ih2[1];
+    rc[RC_DT] = md.dt;
+    rc[RC_TG] = 2.0 * md.gamma * md.dt;
+    rc[RC_CXY] = ih2[0] * ih2[1];
+    for (int i = 0; i < RC_N; ++i) md.rcf[i] = (float)rc[i];
 }
 
 void fill_member_table(ch_ctx* ctx)

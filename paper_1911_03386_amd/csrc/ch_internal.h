@@ -34,6 +34,28 @@ struct AxisCoef {
     double W[4];                     // (I - A^n)^{-1}, n = line length
 };
 
+// The same coefficients rounded to FP32 once on the host, for the FP32
+// kernels (no conversions in a kernel's prologue).
+struct AxisCoefF {
+    float a1, a2, ikappa, inv_n;
+    float E1[2];
+    float M[4];
+    float Mp[kMaxScanLevels][4];
+    float W[4];
+};
+
+// Products of the member's parameters that the RHS uses, formed once on the
+// host in FP64 (in the order written) and also rounded to FP32.
+enum : int {
+    RC_DX, RC_DY, RC_DZ,     // dt / h_d^2
+    RC_GXY, RC_GXZ, RC_GYZ,  // 2 gamma dt / (h_d^2 h_e^2)
+    RC_AX4, RC_AY4,          // gamma dt / h_x^4, gamma dt / h_y^4 (Crank-Nicolson)
+    RC_IHX2, RC_IHY2,        // 1 / h_x^2, 1 / h_y^2
+    RC_DT, RC_TG,            // dt, 2 gamma dt
+    RC_CXY,                  // 1 / (h_x^2 h_y^2)
+    RC_N
+};
+
 struct MemberDev {
     int64_t off;       // element offset of this member in the field arrays
     int64_t sites;
@@ -42,6 +64,9 @@ struct MemberDev {
     double gamma, dt;
     double vol;        // prod h
     AxisCoef ax[3];
+    AxisCoefF axf[3];
+    double rc[RC_N];
+    float rcf[RC_N];
 };
 
 // A class whose members have consecutive ids (every class of a uniform

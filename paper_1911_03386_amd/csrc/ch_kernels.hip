@@ -142,8 +142,22 @@ struct LineCoef {
     T W[4];
 };
 
+// A member's coefficients in the kernel's precision (no conversions in the kernel)
 template <typename T>
-__device__ __forceinline__ void load_coef(LineCoef<T>& c, const AxisCoef& s, int P)
+struct CoefOf;
+template <>
+struct CoefOf<double> {
+    static __device__ __forceinline__ const AxisCoef& ax(const MemberDev& m, int a) { return m.ax[a]; }
+    static __device__ __forceinline__ const double* rc(const MemberDev& m) { return m.rc; }
+};
+template <>
+struct CoefOf<float> {
+    static __device__ __forceinline__ const AxisCoefF& ax(const MemberDev& m, int a) { return m.axf[a]; }
+    static __device__ __forceinline__ const float* rc(const MemberDev& m) { return m.rcf; }
+};
+
+template <typename T, typename AC>
+__device__ __forceinline__ void load_coef(LineCoef<T>& c, const AC& s, int P)
 {
     c.a1 = (T)s.a1;
     c.a2 = (T)s.a2;
@@ -857,14 +871,11 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     const T* cb = sC + PL0 * planeStride + (rl0 + YLO) * pitch + j * (CX + PADE);
 #define AT(dz, dy, m) cb[(dz) * planeStride + (dy) * pitch + (m) + ((m) / CX) * PADE]
 
-    const T ihx2 = (T)md.ih2[0], ihy2 = (T)md.ih2[1];
-    const T dt = (T)md.dt, tg = (T)(2.0 * md.gamma * md.dt);
-    const T cxy = (T)(md.ih2[0] * md.ih2[1]);
     // folded coefficients of the RHS
-    const T cdx = (T)(md.dt * md.ih2[0]), cdy = (T)(md.dt * md.ih2[1]), cdz = (T)(md.dt * md.ih2[2]);
-    const T gxy = (T)(2.0 * md.gamma * md.dt * md.ih2[0] * md.ih2[1]);
-    const T gxz = (T)(2.0 * md.gamma * md.dt * md.ih2[0] * md.ih2[2]);
-    const T gyz = (T)(2.0 * md.gamma * md.dt * md.ih2[1] * md.ih2[2]);
+    const T* rc = CoefOf<T>::rc(md);
+    const T ihx2 = rc[RC_IHX2], ihy2 = rc[RC_IHY2], dt = rc[RC_DT], tg = rc[RC_TG], cxy = rc[RC_CXY];
+    const T cdx = rc[RC_DX], cdy = rc[RC_DY], cdz = rc[RC_DZ];
+    const T gxy = rc[RC_GXY], gxz = rc[RC_GXZ], gyz = rc[RC_GYZ];
 
     // The RHS is formed on every lane: lines past the end of a ragged last
     // band read staged rows that exist (R + 3 are allocated) and their
@@ -874,8 +885,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     if (solve) {
         auto at = [&](int dz, int dy, int m) { return AT(dz, dy, m); };
         if (CN) {
-            const T ax4 = (T)(md.gamma * md.dt * md.ih2[0] * md.ih2[0]);
-            const T ay4 = (T)(md.gamma * md.dt * md.ih2[1] * md.ih2[1]);
+            const T ax4 = rc[RC_AX4], ay4 = rc[RC_AY4];
 #pragma unroll
             for (int k = 0; k < CX; ++k)
 #pragma unroll
@@ -905,7 +915,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
     T mean[RL];
     if (solve) {
         LineCoef<T> cf;
-        load_coef(cf, md.ax[0], P);
+        load_coef(cf, CoefOf<T>::ax(md, 0), P);
         ScanLanes SL;
         make_lanes(SL, lane, g * P, P);
         // the line mean passes through (I + rho D^4)^{-1} unchanged: take it out
@@ -930,7 +940,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
         }
 #pragma unroll
         for (int q = 0; q < RL; ++q) {
-            mean[q] = lane_get(SL.last, csum[q]) * (T)md.ax[0].inv_n;
+            mean[q] = lane_get(SL.last, csum[q]) * CoefOf<T>::ax(md, 0).inv_n;
 #pragma unroll
             for (int k = 0; k < CX; ++k) v[q][k] -= mean[q];
         }
@@ -1057,8 +1067,8 @@ __global__ void __launch_bounds__(kPassAThreads) passA_wide_kernel(PassAArgs a)
             v[0][k] = cb[m + (m / CX) * PADE];
         }
     } else if (solve) {
-        const T cdx = (T)(md.dt * md.ih2[0]), cdy = (T)(md.dt * md.ih2[1]);
-        const T gxy = (T)(2.0 * md.gamma * md.dt * md.ih2[0] * md.ih2[1]);
+        const T* rc = CoefOf<T>::rc(md);
+        const T cdx = rc[RC_DX], cdy = rc[RC_DY], gxy = rc[RC_GXY];
         auto at = [&](int, int dy, int m) { return cb[dy * pitch + m + (m / CX) * PADE]; };
 #pragma unroll
         for (int k = 0; k < CX; ++k) v[0][k] = rhs_site<T, 2>(at, 0, k + HALO, cdx, cdy, T(0), gxy, T(0), T(0));
@@ -1072,12 +1082,12 @@ __global__ void __launch_bounds__(kPassAThreads) passA_wide_kernel(PassAArgs a)
     // ---- x-line solves across the line's wavefronts ------------------------
     T mean = T(0);
     if (solve) {
-        const AxisCoef& ac = md.ax[0];
+        const auto& ac = CoefOf<T>::ax(md, 0);
         LineCoef<T> cf;
         load_coef(cf, ac, 64);
         T A64[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) A64[i] = (T)ac.Mp[kWaveScanLevels][i];
+        for (int i = 0; i < 4; ++i) A64[i] = ac.Mp[kWaveScanLevels][i];
         ScanLanes SL;
         make_lanes(SL, lane, 0, 64);
         // the line mean: chunk sums scanned inside the wavefront, the
@@ -1095,7 +1105,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_wide_kernel(PassAArgs a)
         __syncthreads();
         T tot = T(0);
         for (int w = 0; w < WL; ++w) tot += sst[li * WL + w][0];
-        mean = tot * (T)ac.inv_n;
+        mean = tot * ac.inv_n;
 #pragma unroll
         for (int k = 0; k < CX; ++k) v[0][k] -= mean;
         __syncthreads();  // sst is rewritten below
@@ -1292,8 +1302,8 @@ __global__ void __launch_bounds__(kPassAThreads) rhs_tile_kernel(PassAArgs a)
         diag_sums<T, 2, CT, 1>(at, 1u, md, a.conv, needF, needG, pF, pS, pG);
     }
     if (store && ok) {
-        const T cdx = (T)(md.dt * md.ih2[0]), cdy = (T)(md.dt * md.ih2[1]);
-        const T gxy = (T)(2.0 * md.gamma * md.dt * md.ih2[0] * md.ih2[1]);
+        const T* rc = CoefOf<T>::rc(md);
+        const T cdx = rc[RC_DX], cdy = rc[RC_DY], gxy = rc[RC_GXY];
         auto at = [&](int, int dy, int m) { return cb[dy * PITCH + m + (m / CT) * PADE]; };
         T v[CT];
 #pragma unroll
@@ -1470,10 +1480,9 @@ __global__ void __launch_bounds__(kPassAThreads) passA_multi_kernel(PassAArgs a)
     const int cb_off = (rl0 + 1) * pitch + j * (CX + PADE);
 
     // folded coefficients of the RHS
-    const T cdx = (T)(md.dt * md.ih2[0]), cdy = (T)(md.dt * md.ih2[1]), cdz = (T)(md.dt * md.ih2[2]);
-    const T gxy = (T)(2.0 * md.gamma * md.dt * md.ih2[0] * md.ih2[1]);
-    const T gxz = (T)(2.0 * md.gamma * md.dt * md.ih2[0] * md.ih2[2]);
-    const T gyz = (T)(2.0 * md.gamma * md.dt * md.ih2[1] * md.ih2[2]);
+    const T* rc = CoefOf<T>::rc(md);
+    const T cdx = rc[RC_DX], cdy = rc[RC_DY], cdz = rc[RC_DZ];
+    const T gxy = rc[RC_GXY], gxz = rc[RC_GXZ], gyz = rc[RC_GYZ];
 
     double pF = 0.0, pS = 0.0, pG = 0.0;
     for (int u = 0; u < nunits; ++u) {
@@ -1542,7 +1551,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_multi_kernel(PassAArgs a)
 
         if (solve) {
             LineCoef<T> cf;
-            load_coef(cf, md.ax[0], P);
+            load_coef(cf, CoefOf<T>::ax(md, 0), P);
             ScanLanes SL;
             make_lanes(SL, lane, g * P, P);
             T mean[RL], csum[RL];
@@ -1565,7 +1574,7 @@ __global__ void __launch_bounds__(kPassAThreads) passA_multi_kernel(PassAArgs a)
             }
 #pragma unroll
             for (int q = 0; q < RL; ++q) {
-                mean[q] = lane_get(SL.last, csum[q]) * (T)md.ax[0].inv_n;
+                mean[q] = lane_get(SL.last, csum[q]) * CoefOf<T>::ax(md, 0).inv_n;
 #pragma unroll
                 for (int k = 0; k < CX; ++k) v[q][k] -= mean[q];
             }
@@ -1699,15 +1708,15 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
 #pragma unroll
     for (int k = 0; k < CY; ++k) v[k] = colok ? buf_load<T>(rsrc, voff, k * sstep) : T(0);
 
-    const AxisCoef& ac = md.ax[a.axis];
-    const T a1 = (T)ac.a1, a2 = (T)ac.a2, ik = (T)ac.ikappa;
+    const auto& ac = CoefOf<T>::ax(md, a.axis);
+    const T a1 = ac.a1, a2 = ac.a2, ik = ac.ikappa;
     // the scan's 2x2 matrices live in LDS (read as broadcasts where they are
     // used), which keeps them out of the scalar registers
     __shared__ T sco[(kMaxScanLevels + 1) * 4];  // Mp[0..6], then W
     if (tid < kMaxScanLevels * 4)
-        sco[tid] = (T)ac.Mp[tid >> 2][tid & 3];
+        sco[tid] = ac.Mp[tid >> 2][tid & 3];
     else if (tid < (kMaxScanLevels + 1) * 4)
-        sco[tid] = (T)ac.W[tid - kMaxScanLevels * 4];
+        sco[tid] = ac.W[tid - kMaxScanLevels * 4];
     const T* W = sco + kMaxScanLevels * 4;
 
     // causal recursion.  The line mean m passes through the solve unchanged;
@@ -1718,7 +1727,7 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
     // its P chunks in LDS (log2 P levels, ping-pong buffers, one barrier per
     // level) with the powers M^(2^s) of the chunk transfer matrix; the ring is
     // closed with (I - A^n)^{-1} as in the x-solve.
-    const T E10 = (T)ac.E1[0], E11 = (T)ac.E1[1];
+    const T E10 = ac.E1[0], E11 = ac.E1[1];
     auto Mp = [&](int l) -> const T* { return sco + 4 * l; };
     T e0, e1, csum = T(0);
 #pragma unroll
@@ -1730,7 +1739,7 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
     // the line mean: every thread of the column sums the P chunk sums in order
     T tot = T(0);
     for (int q = 0; q < P; ++q) tot += sS[q * a.b + c];
-    const T m = tot * (T)ac.inv_n;
+    const T m = tot * ac.inv_n;
     e0 -= m * E10;
     e1 -= m * E11;
     // inclusive scan S_j = f_j + M S_{j-1} over the chunks of the column
