@@ -525,7 +525,44 @@ __device__ __forceinline__ void stage_rows(T* sC, __amdgpu_buffer_rsrc_t rC, int
     const int nrows_all = npl * nrows;
     const int nseg = (nvec + 63) >> 6;
     constexpr int NB = 8;
-    if constexpr (DIM == 2) {
+    // a segment of 64 vectors holds whole chunks: its LDS span is SEGW, and a
+    // lane's vector sits at the same offset `ll` in every segment
+    constexpr int SEGW = 64 * VEC + (64 * VEC / CX) * PADE;
+    static_assert((64 * VEC) % CX == 0, "segments hold whole chunks");
+    const int lx = lane * VEC + HALO;
+    const int ll = lx + (lx / CX) * PADE;
+    const int lv = lane * VEC * (int)sizeof(T);
+    if (DIM == 2 && (nvec & 63) == 0) {
+        // one plane, every lane has a vector in every segment: per vector only
+        // the wave-uniform row and segment advance
+        int r = wv, seg = 0;  // wave-uniform cursor (row, segment)
+        while (r < nrows) {
+            VT val[NB];
+            int dst[NB];
+            bool use[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                use[i] = r < nrows;
+                dst[i] = r * pitch + seg * SEGW;
+                if (use[i]) {
+                    const int rowo = wrapi(y0 - ylo + r, ny) * nx + seg * 64 * VEC;  // wave-uniform
+                    val[i] = buf_load16<VT>(rC, lv, rowo * (int)sizeof(T));
+                    if (++seg == nseg) {
+                        seg = 0;
+                        r += nwaves;
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+                if (use[i]) {
+                    T e[VEC];
+                    vec_get<T>(val[i], e);
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) sC[dst[i] + ll + q] = e[q];
+                }
+        }
+    } else if constexpr (DIM == 2) {
         // one plane: the wavefront's rows are wv, wv + nwaves, ...
         int r = wv, seg = 0;  // wave-uniform cursor (row, segment)
         while (r < nrows) {
@@ -719,6 +756,36 @@ __device__ __forceinline__ void write_back(T* so, int pitch, const T (&v)[RL][CX
     const int nseg = (nvec + 63) >> 6;
     const int l1 = min(wv * rpw + rpw, Ract);
     constexpr int NB = 8;
+    constexpr int SEGW = 64 * VEC + (64 * VEC / CX) * PADE;  // LDS span of a segment of 64 vectors
+    static_assert((64 * VEC) % CX == 0, "segments hold whole chunks");
+    if ((nvec & 63) == 0) {
+        // every lane has a vector in every segment (see stage_rows)
+        const int lx = lane * VEC + HALO;
+        const int ll = lx + (lx / CX) * PADE;
+        const int lv = lane * VEC * (int)sizeof(T);
+        int l = wv * rpw, seg = 0;  // wave-uniform cursor (line, segment)
+        while (l < l1) {
+            VT val[NB];
+            int row[NB];  // byte offset of the line's segment in the output (wave-uniform)
+            bool use[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                use[i] = l < l1;
+                row[i] = (out0 + l * nx + seg * 64 * VEC) * (int)sizeof(T);
+                if (use[i]) {
+                    val[i] = vec_make<T>(so + l * pitch + seg * SEGW + ll);
+                    if (++seg == nseg) {
+                        seg = 0;
+                        ++l;
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+                if (use[i]) buf_store16<VT>(val[i], rout, lv, row[i]);
+        }
+        return;
+    }
     int l = wv * rpw, seg = 0;  // wave-uniform cursor (line, segment)
     while (l < l1) {
         VT val[NB];
