@@ -1771,9 +1771,11 @@ __global__ void __launch_bounds__(kColMaxThreads) col_kernel(ColArgs a)
     const int voff = (int)(((int64_t)j * CY * st + c) * (int64_t)sizeof(T));
     const int sstep = (int)(st * (int64_t)sizeof(T));
 
+    // every thread loads (a thread past the block's columns reads chunk 0 of
+    // column c, in range, and its values are never summed, scanned or stored)
     T v[CY];
 #pragma unroll
-    for (int k = 0; k < CY; ++k) v[k] = colok ? buf_load<T>(rsrc, voff, k * sstep) : T(0);
+    for (int k = 0; k < CY; ++k) v[k] = buf_load<T>(rsrc, voff, k * sstep);
 
     const auto& ac = CoefOf<T>::ax(md, a.axis);
     const T a1 = ac.a1, a2 = ac.a2, ik = ac.ikappa;
