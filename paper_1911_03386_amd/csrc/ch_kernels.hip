@@ -1086,7 +1086,11 @@ __global__ void __launch_bounds__(kPassAThreads) passA_wide_kernel(PassAArgs a)
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* sC = reinterpret_cast<T*>(lds_raw);
     __shared__ double red[kPassAThreads / 64][3];
-    __shared__ T sst[kPassAThreads / 64][2];  // per wavefront: scan end state (or chunk-sum total)
+    // per wavefront: chunk-sum total, and the end states of the two scans
+    // (separate arrays, so that no barrier guards their reuse)
+    __shared__ T ssum[kPassAThreads / 64];
+    __shared__ T sfw[kPassAThreads / 64][2];
+    __shared__ T sbw[kPassAThreads / 64][2];
 
     constexpr int PADE = PadOf<T>::v;
     constexpr int VEC = Vec16<T>::n;
@@ -1168,14 +1172,13 @@ __global__ void __launch_bounds__(kPassAThreads) passA_wide_kernel(PassAArgs a)
             const T y = lane_get(SL.up[s], cs);
             if (lane >= (1 << s)) cs += y;
         }
-        if (lane == 63) sst[wv][0] = cs;
+        if (lane == 63) ssum[wv] = cs;
         __syncthreads();
         T tot = T(0);
-        for (int w = 0; w < WL; ++w) tot += sst[li * WL + w][0];
+        for (int w = 0; w < WL; ++w) tot += ssum[li * WL + w];
         mean = tot * ac.inv_n;
 #pragma unroll
         for (int k = 0; k < CX; ++k) v[0][k] -= mean;
-        __syncthreads();  // sst is rewritten below
 
         // causal recursion
         T e0, e1;
@@ -1190,8 +1193,8 @@ __global__ void __launch_bounds__(kPassAThreads) passA_wide_kernel(PassAArgs a)
             }
         }
         if (lane == 63) {
-            sst[wv][0] = e0;
-            sst[wv][1] = e1;
+            sfw[wv][0] = e0;
+            sfw[wv][1] = e1;
         }
         __syncthreads();
         {
@@ -1202,8 +1205,8 @@ __global__ void __launch_bounds__(kPassAThreads) passA_wide_kernel(PassAArgs a)
                     U1 = S1;
                 }
                 mv(A64, S0, S1);
-                S0 += sst[li * WL + w][0];
-                S1 += sst[li * WL + w][1];
+                S0 += sfw[li * WL + w][0];
+                S1 += sfw[li * WL + w][1];
             }
             T r0 = cf.W[0] * S0 + cf.W[1] * S1, r1 = cf.W[2] * S0 + cf.W[3] * S1;
             for (int w = 0; w < wl; ++w) mv(A64, r0, r1);
@@ -1219,7 +1222,6 @@ __global__ void __launch_bounds__(kPassAThreads) passA_wide_kernel(PassAArgs a)
             }
             fwd_true(v[0], cf.a1, cf.a2, p0 + r0, p1 + r1, T(0));
         }
-        __syncthreads();  // sst is rewritten below
 
         // anti-causal recursion
         bwd_zero(v[0], cf.a1, cf.a2, e0, e1);
@@ -1233,8 +1235,8 @@ __global__ void __launch_bounds__(kPassAThreads) passA_wide_kernel(PassAArgs a)
             }
         }
         if (lane == 0) {
-            sst[wv][0] = e0;
-            sst[wv][1] = e1;
+            sbw[wv][0] = e0;
+            sbw[wv][1] = e1;
         }
         __syncthreads();
         {
@@ -1245,8 +1247,8 @@ __global__ void __launch_bounds__(kPassAThreads) passA_wide_kernel(PassAArgs a)
                     U1 = S1;
                 }
                 mv(A64, S0, S1);
-                S0 += sst[li * WL + w][0];
-                S1 += sst[li * WL + w][1];
+                S0 += sbw[li * WL + w][0];
+                S1 += sbw[li * WL + w][1];
             }
             T r0 = cf.W[0] * S0 + cf.W[1] * S1, r1 = cf.W[2] * S0 + cf.W[3] * S1;
             for (int w = WL - 1; w > wl; --w) mv(A64, r0, r1);
