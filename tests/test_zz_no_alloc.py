@@ -76,3 +76,14 @@ def test_static_rejects_oversize():
     with pytest.raises(ch.ChError) as e:
         ch.ch_step_static(big, ch.CH_F32_BULK, field, 1)
     assert e.value.status == ch.CH_ENOMEM and "static scratch" in str(e.value)
+
+
+@pytest.mark.parametrize("prec", [ch.CH_F64, ch.CH_F32_BULK], ids=["f64-split", "f32-wide"])
+def test_static_lines_beyond_one_wavefront(prec):
+    """8192-point x-lines (256 chunks over 4 wavefronts; FP64 in the split
+    form, whose diagnostics come from the RHS tiles) through both paths."""
+    torch.cuda.set_device(0)
+    h = 2 * np.pi / 512
+    descs = [ch.make_desc((8192, 8), 0.01, 5e-4, c0=0.1 * m, noise=0.1, seed=600 + m, L=(8192 * h, 8 * h))
+             for m in range(2)]
+    _check(descs, prec, 12)
