@@ -461,3 +461,24 @@ def test_caller_captured_graph_replays():
         np.testing.assert_array_equal(ens.beta_series(m), ref.beta_series(m))
     ens.close()
     ref.close()
+
+
+@pytest.mark.parametrize("prec", [CH_F64, CH_F32_BULK], ids=["f64", "f32"])
+def test_reduction_accuracy_on_identical_fields(prec):
+    """F, <C> and the identity term at t = 0 are sums over the same field on
+    both sides (the FP32-bulk field rounded to FP32 for the oracle), so their
+    difference is the reductions' rounding alone: the oracle's sums are exactly
+    rounded, the library's two-level ones stay within 1e-13 of them."""
+    d = make_desc((512, 512), 0.01, 1e-3, c0=0.1, noise=0.3, seed=21)
+    ens = Ensemble([d], prec=prec, cadence=10, max_samples=2)
+    ens.init_random()
+    ens.step(10)
+    row = ens.beta_series(0)[0]
+    ens.close()
+    C0 = oracle.init_field((512, 512), d.c0, d.noise, d.seed)
+    if prec == CH_F32_BULK:
+        C0 = C0.astype(np.float32).astype(np.float64)
+    _, S = oracle.run_series(C0, d.gamma, d.dt, 10, K=10)
+    errs = {name: abs(row[c] - S[0, c]) / abs(S[0, c]) for name, c in (("F", 1), ("<C>", 5), ("G_id", 3))}
+    print("relative differences at t = 0:", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert max(errs.values()) <= 1e-13, errs
