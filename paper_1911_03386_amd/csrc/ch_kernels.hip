@@ -251,6 +251,53 @@ __device__ __forceinline__ double lane_get(int addr, double v)
     return *reinterpret_cast<double*>(&r);
 }
 
+// Sum over each aligned group of P lanes (P a power of two, at most 64) by
+// butterflies: DPP lane exchanges inside rows of 16 (xor 1, xor 2, then the
+// half-row and row mirrors, which pair the group halves in the same way), a
+// swizzle across rows for 32 and a permute across halves for 64.  Each level
+// adds a lane's value and its partner's, so every lane of the group ends with
+// the same bits.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float lane_x(float v)
+{
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_x(double v)
+{
+    int2 w = *reinterpret_cast<int2*>(&v);
+    w.x = dpp_i<CTRL>(w.x);
+    w.y = dpp_i<CTRL>(w.y);
+    return *reinterpret_cast<double*>(&w);
+}
+__device__ __forceinline__ float swz16(float v)
+{
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));  // lane ^ 16 within 32
+}
+__device__ __forceinline__ double swz16(double v)
+{
+    int2 w = *reinterpret_cast<int2*>(&v);
+    w.x = __builtin_amdgcn_ds_swizzle(w.x, 0x401F);
+    w.y = __builtin_amdgcn_ds_swizzle(w.y, 0x401F);
+    return *reinterpret_cast<double*>(&w);
+}
+template <typename T>
+__device__ __forceinline__ T group_sum(T x, int P, int lane)
+{
+    if (P >= 2) x += lane_x<0xB1>(x);   // quad_perm [1,0,3,2]
+    if (P >= 4) x += lane_x<0x4E>(x);   // quad_perm [2,3,0,1]
+    if (P >= 8) x += lane_x<0x141>(x);  // row_half_mirror
+    if (P >= 16) x += lane_x<0x140>(x); // row_mirror
+    if (P >= 32) x += swz16(x);
+    if (P >= 64) x += lane_get(((lane ^ 32) & 63) << 2, x);
+    return x;
+}
+
 // Source addresses of the wavefront scans: up[s] = lane - 2^s, dn[s] = lane + 2^s
 // (wrapped; only read where the source lies in the same line), and the first
 // and last lane of the line.
@@ -994,20 +1041,27 @@ __global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
 #pragma unroll
             for (int k = 0; k < CX; ++k) csum[q] += v[q][k];
         }
+        if ((P & (P - 1)) == 0) {
 #pragma unroll
-        for (int s = 0; s < kWaveScanLevels; ++s) {
-            const int d = 1 << s;
-            if (d < P) {
+            for (int q = 0; q < RL; ++q) csum[q] = group_sum(csum[q], P, lane);
+        } else {
 #pragma unroll
-                for (int q = 0; q < RL; ++q) {
-                    const T y = lane_get(SL.up[s], csum[q]);
-                    if (j >= d) csum[q] += y;
+            for (int s = 0; s < kWaveScanLevels; ++s) {
+                const int d = 1 << s;
+                if (d < P) {
+#pragma unroll
+                    for (int q = 0; q < RL; ++q) {
+                        const T y = lane_get(SL.up[s], csum[q]);
+                        if (j >= d) csum[q] += y;
+                    }
                 }
             }
+#pragma unroll
+            for (int q = 0; q < RL; ++q) csum[q] = lane_get(SL.last, csum[q]);
         }
 #pragma unroll
         for (int q = 0; q < RL; ++q) {
-            mean[q] = lane_get(SL.last, csum[q]) * CoefOf<T>::ax(md, 0).inv_n;
+            mean[q] = csum[q] * CoefOf<T>::ax(md, 0).inv_n;
 #pragma unroll
             for (int k = 0; k < CX; ++k) v[q][k] -= mean[q];
         }
@@ -1630,20 +1684,27 @@ __global__ void __launch_bounds__(kPassAThreads) passA_multi_kernel(PassAArgs a)
 #pragma unroll
                 for (int k = 0; k < CX; ++k) csum[q] += v[q][k];
             }
+            if ((P & (P - 1)) == 0) {
 #pragma unroll
-            for (int s = 0; s < kWaveScanLevels; ++s) {
-                const int d = 1 << s;
-                if (d < P) {
+                for (int q = 0; q < RL; ++q) csum[q] = group_sum(csum[q], P, lane);
+            } else {
 #pragma unroll
-                    for (int q = 0; q < RL; ++q) {
-                        const T y = lane_get(SL.up[s], csum[q]);
-                        if (j >= d) csum[q] += y;
+                for (int s = 0; s < kWaveScanLevels; ++s) {
+                    const int d = 1 << s;
+                    if (d < P) {
+#pragma unroll
+                        for (int q = 0; q < RL; ++q) {
+                            const T y = lane_get(SL.up[s], csum[q]);
+                            if (j >= d) csum[q] += y;
+                        }
                     }
                 }
+#pragma unroll
+                for (int q = 0; q < RL; ++q) csum[q] = lane_get(SL.last, csum[q]);
             }
 #pragma unroll
             for (int q = 0; q < RL; ++q) {
-                mean[q] = lane_get(SL.last, csum[q]) * CoefOf<T>::ax(md, 0).inv_n;
+                mean[q] = csum[q] * CoefOf<T>::ax(md, 0).inv_n;
 #pragma unroll
                 for (int k = 0; k < CX; ++k) v[q][k] -= mean[q];
             }
