@@ -1215,17 +1215,13 @@ __global__ void __launch_bounds__(kPassAThreads) passA_wide_kernel(PassAArgs a)
         for (int i = 0; i < 4; ++i) A64[i] = ac.Mp[kWaveScanLevels][i];
         ScanLanes SL;
         make_lanes(SL, lane, 0, 64);
-        // the line mean: chunk sums scanned inside the wavefront, the
+        // the line mean: chunk sums added up inside the wavefront, the
         // wavefront totals added in order (the same order for every wavefront
         // of the line)
         T cs = T(0);
 #pragma unroll
         for (int k = 0; k < CX; ++k) cs += v[0][k];
-#pragma unroll
-        for (int s = 0; s < kWaveScanLevels; ++s) {
-            const T y = lane_get(SL.up[s], cs);
-            if (lane >= (1 << s)) cs += y;
-        }
+        cs = group_sum(cs, 64, lane);
         if (lane == 63) ssum[wv] = cs;
         __syncthreads();
         T tot = T(0);
