@@ -32,6 +32,10 @@
 //                 (y-bands in 2D, z-planes of a y-band through a ring of
 //                 staged planes in 3D), the next unit's rows loading while
 //                 the current one is computed.
+//   passA_wide_kernel  2D x-lines of 128 or 256 chunks, a line held by 2 or
+//                 4 wavefronts whose chunk scans combine through LDS; in the
+//                 split form (rows too long for LDS) it solves lines whose
+//                 RHS rhs_tile_kernel formed over 8 x 256 tiles.
 //   col_kernel    y- or z-lines.  A block owns b adjacent columns; lane
 //                 (column, chunk) holds a contiguous chunk of one line in
 //                 registers, loads are coalesced across columns.
