@@ -196,8 +196,9 @@ ch_status ch_autotune(ch_ctx* ctx, const char* cache_path);
 
 /* Number of size classes and explicit tile shapes for one class.  Members
  * are grouped by dimension and grid shape, in order of first appearance; while
- * there are fewer than four classes, the largest class with at least 8
- * members is split into two classes of consecutive members.  Classes are
+ * there are fewer than four classes, the class with the most sites among
+ * those of at least 8 members is split into two classes of consecutive
+ * members.  Classes are
  * independent and run concurrently on separate streams.  The
  * RHS + x-solve pass: cx = elements per lane of an x-line, rl = x-lines per
  * lane, waves = wavefronts per block, units = work units a block walks

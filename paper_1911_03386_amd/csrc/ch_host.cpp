@@ -34,9 +34,9 @@ bool is_live(const void* p)
 
 constexpr size_t kAlign = 256;
 constexpr size_t kLdsLimit = 160 * 1024 - 1024;  // gfx950: 160 KiB per workgroup, minus statics
-// The size classes of a step run on up to kMaxStreams streams; a class is
-// split in two while there are fewer classes than streams and it has at
-// least 2 * kMinSplit members.
+// The size classes of a step run on up to kMaxStreams streams; the class
+// with the most sites among those of at least 2 * kMinSplit members is split
+// in two while there are fewer classes than streams.
 constexpr int kMaxStreams = 4;
 constexpr int kMaxHistBins = 4096;
 constexpr int kMinSplit = 4;
@@ -404,11 +404,12 @@ void build_classes(const ch_member_desc* members, int32_t m, std::vector<ClassPl
     // Split the largest classes into consecutive runs of members, so that the
     // classes of a step can overlap on separate streams: one class's
     // latency-bound RHS pass with another's bandwidth-bound column sweeps.
+    // Largest means most sites, which evens out the streams' work.
+    auto sites = [](const ClassPlan& c) { return (double)c.members.size() * c.nx * c.ny * c.nz; };
     while ((int)classes.size() < kMaxStreams) {
         int big = -1;
         for (int c = 0; c < (int)classes.size(); ++c)
-            if (classes[c].members.size() >= 2 * (size_t)kMinSplit &&
-                (big < 0 || classes[c].members.size() > classes[big].members.size()))
+            if (classes[c].members.size() >= 2 * (size_t)kMinSplit && (big < 0 || sites(classes[c]) > sites(classes[big])))
                 big = c;
         if (big < 0) break;
         ClassPlan second = classes[big];
