@@ -409,7 +409,8 @@ void build_classes(const ch_member_desc* members, int32_t m, std::vector<ClassPl
     while ((int)classes.size() < kMaxStreams) {
         int big = -1;
         for (int c = 0; c < (int)classes.size(); ++c)
-            if (classes[c].members.size() >= 2 * (size_t)kMinSplit && (big < 0 || sites(classes[c]) > sites(classes[big])))
+            if (classes[c].members.size() >= 2 * (size_t)kMinSplit &&
+                (big < 0 || sites(classes[c]) > sites(classes[big])))
                 big = c;
         if (big < 0) break;
         ClassPlan second = classes[big];
