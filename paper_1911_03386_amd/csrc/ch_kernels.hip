@@ -920,8 +920,14 @@ __device__ __forceinline__ void rhs_cn_site(const At& at, int q, int m, T ihx2, 
 }
 
 
+// The second launch bound is the wavefronts per SIMD the compiler must leave
+// room for.  The FP32 2D shapes with at most 16 elements per lane fit 80
+// registers without spilling (the unconstrained build takes 83 for c = 16,
+// one wavefront per SIMD fewer than the LDS of a block allows); the others
+// keep the compiler's choice.
 template <typename T, int DIM, int CX, int RL, bool CN>
-__global__ void __launch_bounds__(kPassAThreads) passA_kernel(PassAArgs a)
+__global__ void __launch_bounds__(kPassAThreads, (sizeof(T) == 4 && DIM == 2 && !CN && CX * RL <= 16) ? 6 : 1)
+    passA_kernel(PassAArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* sC = reinterpret_cast<T*>(lds_raw);
